@@ -23,6 +23,7 @@
 #define _USE_MATH_DEFINES
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORACLE_MAX_ORDER 7
@@ -228,27 +229,43 @@ static double wavenumber(long k, long K, double len)
 void oracle_influence_function(const double *len, const int32_t *K, int P,
                                double g, int diff, int alias, double *G)
 {
-    const long Kx = K[0], Ky = K[1], Kz = K[2];
-    const double hx = len[0] / Kx, hy = len[1] / Ky, hz = len[2] / Kz;
+    const long Kd[3] = {K[0], K[1], K[2]};
+    const int na = 2 * alias + 1;
+    /* Per axis, index and alias: the aliased wavenumber q, the assignment
+     * factor sinc(q h / 2)^(2P) and the screening factor exp(-q^2 / 4g^2).
+     * U^2 and exp(-|q|^2 / 4g^2) are products of these per-axis factors. */
+    double *qa[3], *ua[3], *ea[3];
+    for (int d = 0; d < 3; ++d) {
+        const double h = len[d] / Kd[d];
+        qa[d] = malloc(sizeof(double) * Kd[d] * na);
+        ua[d] = malloc(sizeof(double) * Kd[d] * na);
+        ea[d] = malloc(sizeof(double) * Kd[d] * na);
+        for (long i = 0; i < Kd[d]; ++i)
+            for (int m = 0; m < na; ++m) {
+                double q = wavenumber(i, Kd[d], len[d]) + 2.0 * M_PI * (m - alias) / h;
+                qa[d][i * na + m] = q;
+                ua[d][i * na + m] = pow(sinc(0.5 * q * h), 2 * P);
+                ea[d][i * na + m] = exp(-q * q / (4.0 * g * g));
+            }
+    }
     #pragma omp parallel for schedule(dynamic)
-    for (long iz = 0; iz < Kz; ++iz)
-        for (long iy = 0; iy < Ky; ++iy)
-            for (long ix = 0; ix < Kx; ++ix) {
-                double kx = wavenumber(ix, Kx, len[0]);
-                double ky = wavenumber(iy, Ky, len[1]);
-                double kz = wavenumber(iz, Kz, len[2]);
+    for (long iz = 0; iz < Kd[2]; ++iz)
+        for (long iy = 0; iy < Kd[1]; ++iy)
+            for (long ix = 0; ix < Kd[0]; ++ix) {
+                double kx = wavenumber(ix, Kd[0], len[0]);
+                double ky = wavenumber(iy, Kd[1], len[1]);
+                double kz = wavenumber(iz, Kd[2], len[2]);
                 double k2 = kx * kx + ky * ky + kz * kz;
                 double num = 0.0, sum_u2 = 0.0, sum_k2u2 = 0.0;
-                for (int mz = -alias; mz <= alias; ++mz)
-                    for (int my = -alias; my <= alias; ++my)
-                        for (int mx = -alias; mx <= alias; ++mx) {
-                            double qx = kx + 2.0 * M_PI * mx / hx;
-                            double qy = ky + 2.0 * M_PI * my / hy;
-                            double qz = kz + 2.0 * M_PI * mz / hz;
-                            double u2 = pow(sinc(0.5 * qx * hx) * sinc(0.5 * qy * hy) *
-                                            sinc(0.5 * qz * hz), 2 * P);
+                for (int mz = 0; mz < na; ++mz)
+                    for (int my = 0; my < na; ++my)
+                        for (int mx = 0; mx < na; ++mx) {
+                            double qx = qa[0][ix * na + mx], qy = qa[1][iy * na + my], qz = qa[2][iz * na + mz];
+                            double u2 = ua[0][ix * na + mx] * ua[1][iy * na + my] * ua[2][iz * na + mz];
                             double q2 = qx * qx + qy * qy + qz * qz;
-                            double ref = q2 > 0.0 ? 4.0 * M_PI * exp(-q2 / (4.0 * g * g)) / q2 : 0.0;
+                            double ref = q2 > 0.0 ? 4.0 * M_PI * ea[0][ix * na + mx] * ea[1][iy * na + my] *
+                                                    ea[2][iz * na + mz] / q2
+                                                  : 0.0;
                             sum_u2 += u2;
                             sum_k2u2 += q2 * u2;
                             if (diff == 0)
@@ -259,6 +276,11 @@ void oracle_influence_function(const double *len, const int32_t *K, int P,
                 double v = 0.0;
                 if (k2 > 0.0)
                     v = (diff == 0) ? num / (k2 * sum_u2 * sum_u2) : num / (sum_u2 * sum_k2u2);
-                G[(iz * Ky + iy) * Kx + ix] = v;
+                G[(iz * Kd[1] + iy) * Kd[0] + ix] = v;
             }
+    for (int d = 0; d < 3; ++d) {
+        free(qa[d]);
+        free(ua[d]);
+        free(ea[d]);
+    }
 }

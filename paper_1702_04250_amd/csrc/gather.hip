@@ -1,0 +1,266 @@
+// fieldforce: the paper's Distribute-Force (Section 3.1), ik and ad modes,
+// and the adjoint gather of the energy backward.
+//
+//   ik:      F_i = q_i sum_{P^3} wx wy wz (Ex, Ey, Ez)_m
+//   ad:      F_i = -q_i (sum dwx wy wz phi / hx, sum wx dwy wz phi / hy,
+//                        sum wx wy dwz phi / hz)
+//   adjoint: dE/dr_i = q_i grad phi(r_i),
+//            dE/dq_i = phi(r_i) - 2 C g q_i / sqrt(pi) - C pi Q / (V g^2),
+//            both times dL/dE.
+//
+// GPU design: one workgroup per mesh tile.  The tile plus its P - 1 upper
+// halo points of every field mesh is staged in LDS with coalesced loads,
+// then each thread takes one binned charge of the tile's own sub-bricks,
+// evaluates its stencil coefficients in registers and sums the P^3 staged
+// values: rows along x first (unit stride, the paper's inner loop), then
+// rows into planes, planes into the result (the "split atom" idea of the ad
+// kernel: the per-atom epilogue is a few register operations).  Results are
+// written straight to the caller's particle order through the permutation.
+#include "runs.h"
+
+namespace pppm {
+
+namespace {
+
+struct GatherArgs {
+    TileGeo tg;
+    const int* offsets;
+    const void* rec;
+    const int* perm;
+    const void* field;   // ncomp meshes of type R, each ncell long
+    long long ncell;
+    int pitch_x;         // LDS row pitch
+    int rows_y;          // LDS rows per plane
+    double inv_h[3];
+    void* out0;          // forces (ik/ad) or grad_pos (adjoint); N x 3
+    void* out1;          // grad_q (adjoint); N
+    const double* grad_energy;
+    const double* eterms;
+    double self_coef;    // 2 C g / sqrt(pi)
+    double bg_coef;      // C pi / (V g^2)
+};
+
+template <int P, int MODE, typename R, typename TO>
+__global__ __launch_bounds__(512) void k_gather(GatherArgs a)
+{
+    constexpr int NC = (MODE == GATHER_IK) ? 3 : 1;
+    constexpr bool DERIV = (MODE != GATHER_IK);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int lists[3 * MAXL];
+    __shared__ int cnts[3];
+    __shared__ int scratch[17];
+    const TileGeo& tg = a.tg;
+
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tix = tile % tg.ntile[0];
+    const int tiy = (tile / tg.ntile[0]) % tg.ntile[1];
+    const int tiz = tile / (tg.ntile[0] * tg.ntile[1]);
+    const int T0[3] = {tix * tg.B[0], tiy * tg.B[1], tiz * tg.B[2]};
+    const int ext[3] = {min(tg.B[0], tg.K[0] - T0[0]), min(tg.B[1], tg.K[1] - T0[1]),
+                        min(tg.B[2], tg.K[2] - T0[2])};
+
+    R* fld = (R*)smem_raw;
+    const int plane = a.pitch_x * a.rows_y;
+    const int nsl = plane * (tg.B[2] + P - 1);  // one staged mesh
+    int* run_start = (int*)(fld + NC * nsl);
+    int* run_sb = run_start + MAX_RUNS;
+    int* prefix = run_sb + MAX_RUNS;
+
+    // stage tile + upper halo of every field mesh (periodic wrap)
+    {
+        const int sx = ext[0] + P - 1, sy = ext[1] + P - 1, sz = ext[2] + P - 1;
+        const int n = sx * sy * sz;
+        const R* __restrict__ fg = (const R*)a.field;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int lx = i % sx, ly = (i / sx) % sy, lz = i / (sx * sy);
+            int gx = T0[0] + lx, gy = T0[1] + ly, gz = T0[2] + lz;
+            if (gx >= tg.K[0]) gx -= tg.K[0];
+            if (gy >= tg.K[1]) gy -= tg.K[1];
+            if (gz >= tg.K[2]) gz -= tg.K[2];
+            const size_t g = ((size_t)gz * tg.K[1] + gy) * tg.K[0] + gx;
+            const int li = lz * plane + ly * a.pitch_x + lx;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fld[c * nsl + li] = fg[c * a.ncell + g];
+        }
+    }
+    const int nruns = build_runs(tg, T0, ext, 0, a.offsets, lists, cnts, run_start, prefix, run_sb, scratch);
+    if (nruns < 0) return;
+    const int total = prefix[nruns];
+
+    double gE = 1.0, Q = 0.0;
+    if (MODE == GATHER_ADJOINT) {
+        gE = *a.grad_energy;
+        Q = a.eterms[4];
+    }
+
+    using RT = typename Rec<R>::T;
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+        const int r = find_run(prefix, nruns, v);
+        const int p = run_start[r] + (v - prefix[r]);
+        const RT pr = rec[p];
+        const int sbp = run_sb[r];
+        const int sbc[3] = {sbp & 1023, (sbp >> 10) & 1023, sbp >> 20};
+        const R tt[3] = {pr.x, pr.y, pr.z};
+        int l[3];
+        R w[3][P], dw[3][P];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int s;
+            R f;
+            decode_axis<R>(tt[d], sbc[d], tg.K[d], s, f);
+            bspline<P, R, DERIV>(f, w[d], dw[d]);
+            l[d] = s - T0[d];  // own particle: in [0, ext)
+        }
+        const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
+        R o0 = R(0), o1 = R(0), o2 = R(0), o3 = R(0);
+        // z planes in a rolled loop: the plane's z coefficients are always
+        // element 0 of the register arrays, which shift down one per plane
+        // (no dynamic register indexing, P^2 loads in flight at most).
+#pragma unroll 1
+        for (int jz = 0; jz < P; ++jz) {
+            R p0 = R(0), p1 = R(0), p2 = R(0);
+            const R* pl0 = base + jz * plane;
+#pragma unroll
+            for (int jy = 0; jy < P; ++jy) {
+                const R* row = pl0 + jy * a.pitch_x;
+                if (MODE == GATHER_IK) {
+                    R rx = R(0), ry = R(0), rz = R(0);
+#pragma unroll
+                    for (int jx = 0; jx < P; ++jx) {
+                        rx += w[0][jx] * row[jx];
+                        ry += w[0][jx] * row[nsl + jx];
+                        rz += w[0][jx] * row[2 * nsl + jx];
+                    }
+                    p0 += w[1][jy] * rx;
+                    p1 += w[1][jy] * ry;
+                    p2 += w[1][jy] * rz;
+                } else {
+                    R r0 = R(0), r1 = R(0);
+#pragma unroll
+                    for (int jx = 0; jx < P; ++jx) {
+                        const R phi = row[jx];
+                        r0 += w[0][jx] * phi;
+                        r1 += dw[0][jx] * phi;
+                    }
+                    p0 += w[1][jy] * r1;   // -> d/dx
+                    p1 += dw[1][jy] * r0;  // -> d/dy
+                    p2 += w[1][jy] * r0;   // -> d/dz and the potential
+                }
+            }
+            const R wz = w[2][0], dwz = dw[2][0];
+            if (MODE == GATHER_IK) {
+                o0 += wz * p0;
+                o1 += wz * p1;
+                o2 += wz * p2;
+            } else {
+                o0 += wz * p0;
+                o1 += wz * p1;
+                o2 += dwz * p2;
+                o3 += wz * p2;
+            }
+#pragma unroll
+            for (int j = 0; j < P - 1; ++j) {
+                w[2][j] = w[2][j + 1];
+                if (DERIV) dw[2][j] = dw[2][j + 1];
+            }
+        }
+        const int iu = a.perm[p];
+        TO* out = (TO*)a.out0;
+        const R qv = pr.w;
+        if (MODE == GATHER_IK) {
+            out[3 * (size_t)iu + 0] = (TO)(qv * o0);
+            out[3 * (size_t)iu + 1] = (TO)(qv * o1);
+            out[3 * (size_t)iu + 2] = (TO)(qv * o2);
+        } else if (MODE == GATHER_AD) {
+            out[3 * (size_t)iu + 0] = (TO)(-qv * o0 * (R)a.inv_h[0]);
+            out[3 * (size_t)iu + 1] = (TO)(-qv * o1 * (R)a.inv_h[1]);
+            out[3 * (size_t)iu + 2] = (TO)(-qv * o2 * (R)a.inv_h[2]);
+        } else {
+            const double qd = (double)qv;
+            if (out) {
+                out[3 * (size_t)iu + 0] = (TO)(gE * qd * (double)o0 * a.inv_h[0]);
+                out[3 * (size_t)iu + 1] = (TO)(gE * qd * (double)o1 * a.inv_h[1]);
+                out[3 * (size_t)iu + 2] = (TO)(gE * qd * (double)o2 * a.inv_h[2]);
+            }
+            if (a.out1)
+                ((TO*)a.out1)[iu] = (TO)(gE * ((double)o3 - a.self_coef * qd - a.bg_coef * Q));
+        }
+    }
+}
+
+template <int MODE, typename R, typename TO>
+hipError_t dispatch_gather(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const GatherArgs& a)
+{
+    switch (P) {
+    case 2: k_gather<2, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 3: k_gather<3, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 4: k_gather<4, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 5: k_gather<5, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 6: k_gather<6, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 7: k_gather<7, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t dispatch_types(const pppm_plan_s* pl, dim3 grid, dim3 block, size_t lds, const GatherArgs& a)
+{
+    const bool f32io = pl->p.io_dtype == PPPM_F32;
+    const int P = pl->p.order;
+    if (pl->mixed)
+        return f32io ? dispatch_gather<MODE, float, float>(P, grid, block, lds, pl->stream, a)
+                     : dispatch_gather<MODE, float, double>(P, grid, block, lds, pl->stream, a);
+    return f32io ? dispatch_gather<MODE, double, float>(P, grid, block, lds, pl->stream, a)
+                 : dispatch_gather<MODE, double, double>(P, grid, block, lds, pl->stream, a);
+}
+
+int gather_pitch(const pppm_plan_s* pl, const LaunchCfg& c) { return c.tile[0] + pl->p.order - 1; }
+
+}  // namespace
+
+size_t gather_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c, int ncomp)
+{
+    const int P = pl->p.order;
+    const size_t nsl = (size_t)gather_pitch(pl, c) * (c.tile[1] + P - 1) * (c.tile[2] + P - 1);
+    return ncomp * nsl * pl->rsize + 3 * MAX_RUNS * sizeof(int) + sizeof(int);
+}
+
+hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy)
+{
+    const LaunchCfg& c = (mode == GATHER_ADJOINT) ? pl->adjoint_cfg : pl->gather_cfg;
+    const int P = pl->p.order;
+    GatherArgs a{};
+    a.tg = make_tiles(pl, c);
+    a.offsets = pl->offsets;
+    a.rec = pl->records;
+    a.perm = pl->perm;
+    a.ncell = pl->ncell;
+    a.pitch_x = gather_pitch(pl, c);
+    a.rows_y = c.tile[1] + P - 1;
+    for (int d = 0; d < 3; ++d) a.inv_h[d] = 1.0 / pl->geo.h[d];
+    a.out0 = out0;
+    a.out1 = out1;
+    a.grad_energy = grad_energy;
+    a.eterms = pl->eterms;
+    a.self_coef = 2.0 * pl->p.coulomb_c * pl->p.g_ewald / sqrt(M_PI);
+    const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
+    a.bg_coef = pl->p.coulomb_c * M_PI / (V * pl->p.g_ewald * pl->p.g_ewald);
+    const size_t rs = pl->rsize;
+    dim3 grid(a.tg.ntiles), block(c.threads);
+    switch (mode) {
+    case GATHER_IK:
+        a.field = pl->field;
+        return dispatch_types<GATHER_IK>(pl, grid, block, gather_lds_bytes(pl, c, 3), a);
+    case GATHER_AD:
+        a.field = pl->field;
+        return dispatch_types<GATHER_AD>(pl, grid, block, gather_lds_bytes(pl, c, 1), a);
+    default:
+        // phi lives after the ncomp field meshes for ik plans, first for ad plans
+        a.field = (const char*)pl->field + (pl->p.diff == PPPM_DIFF_IK ? 3 * pl->ncell * rs : 0);
+        return dispatch_types<GATHER_ADJOINT>(pl, grid, block, gather_lds_bytes(pl, c, 1), a);
+    }
+}
+
+}  // namespace pppm

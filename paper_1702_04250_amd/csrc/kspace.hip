@@ -1,0 +1,258 @@
+// k-space part of the Poisson step (Equation 2; Section 3.2), around the
+// rocFFT transforms: the influence function (built once per plan), the
+// influence-function multiply with the ik derivative, and the FP64 energy
+// reduction.
+//
+// Influence function (the paper leaves the Green function unspecified; this
+// is the optimal one for order-P B-spline assignment, minimising the RMS
+// force error): with U(k) = prod_d sinc(k_d h_d / 2)^P,
+// R(k) = 4 pi exp(-k^2/4g^2) / k^2 and aliases k_m = k + 2 pi m / h, |m_d| <= 2,
+//   ik: G = sum_m U^2(k_m) (k . k_m) R(k_m) / (|k|^2 [sum_m U^2(k_m)]^2)
+//   ad: G = sum_m U^2(k_m) |k_m|^2 R(k_m) / ([sum_m U^2(k_m)] [sum_m |k_m|^2 U^2(k_m)])
+// G(0) = 0.  The plan stores (C / V) G on the half spectrum of the real FFT.
+#include "device_common.h"
+
+namespace pppm {
+
+namespace {
+
+constexpr int ALIAS = 2;
+constexpr int NA = 2 * ALIAS + 1;
+
+struct KGeo {
+    int K[3];
+    int nxh;        // Kx / 2 + 1
+    double len[3];
+    double h[3];
+};
+
+__device__ __forceinline__ void store_c(float2* p, double re, double im) { *p = make_float2((float)re, (float)im); }
+__device__ __forceinline__ void store_c(double2* p, double re, double im) { *p = make_double2(re, im); }
+
+// FFT-order wavenumber index: n in [-K/2, K/2)
+__device__ __forceinline__ int fft_index(int i, int K) { return (2 * i < K) ? i : i - K; }
+
+__global__ __launch_bounds__(KSPACE_THREADS) void k_influence(KGeo kg, long long nspec, int P, double g,
+                                                               int diff, double scale, double* __restrict__ G)
+{
+    const long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x;
+    if (idx >= nspec) return;
+    const int ix = (int)(idx % kg.nxh);
+    const int iy = (int)((idx / kg.nxh) % kg.K[1]);
+    const int iz = (int)(idx / ((long long)kg.nxh * kg.K[1]));
+    const int ii[3] = {ix, iy, iz};
+    const double two_pi = 2.0 * M_PI;
+    double kk[3];
+    double qv[3][NA], u2[3][NA], ex[3][NA];
+    for (int d = 0; d < 3; ++d) {
+        kk[d] = two_pi * (double)fft_index(ii[d], kg.K[d]) / kg.len[d];
+        for (int m = 0; m < NA; ++m) {
+            const double q = kk[d] + two_pi * (double)(m - ALIAS) / kg.h[d];
+            const double x = 0.5 * q * kg.h[d];
+            const double s = (x == 0.0) ? 1.0 : sin(x) / x;
+            double p = 1.0;
+            for (int e = 0; e < 2 * P; ++e) p *= s;
+            qv[d][m] = q;
+            u2[d][m] = p;
+            ex[d][m] = exp(-q * q / (4.0 * g * g));
+        }
+    }
+    const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
+    double out = 0.0;
+    if (k2 > 0.0) {
+        double num = 0.0, sum_u2 = 0.0, sum_k2u2 = 0.0;
+        for (int mz = 0; mz < NA; ++mz)
+            for (int my = 0; my < NA; ++my)
+                for (int mx = 0; mx < NA; ++mx) {
+                    const double qx = qv[0][mx], qy = qv[1][my], qz = qv[2][mz];
+                    const double u = u2[0][mx] * u2[1][my] * u2[2][mz];
+                    const double q2 = qx * qx + qy * qy + qz * qz;
+                    const double ref = (q2 > 0.0) ? 4.0 * M_PI * ex[0][mx] * ex[1][my] * ex[2][mz] / q2 : 0.0;
+                    sum_u2 += u;
+                    sum_k2u2 += q2 * u;
+                    num += (diff == PPPM_DIFF_IK) ? u * (kk[0] * qx + kk[1] * qy + kk[2] * qz) * ref
+                                                  : u * q2 * ref;
+                }
+        out = (diff == PPPM_DIFF_IK) ? num / (k2 * sum_u2 * sum_u2) : num / (sum_u2 * sum_k2u2);
+    }
+    G[idx] = scale * out;
+}
+
+// phi_hat = G' rho_hat; ik: E_hat_d = -i kappa_d G' rho_hat (kappa = 0 on the
+// Nyquist planes); energy partial sums 1/2 sum w_k G' |rho_hat|^2 where w_k
+// counts the Hermitian partner of each half-spectrum point.
+template <typename C>
+__global__ __launch_bounds__(KSPACE_THREADS) void k_solve(KGeo kg, long long nspec, int mode,
+                                                           const double2* __restrict__ rho_hat,
+                                                           const double* __restrict__ G, C* __restrict__ spec,
+                                                           double* __restrict__ epart)
+{
+    __shared__ double red[KSPACE_THREADS / 64];
+    double e = 0.0;
+    const double two_pi = 2.0 * M_PI;
+    for (long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x; idx < nspec;
+         idx += (long long)gridDim.x * KSPACE_THREADS) {
+        const int ix = (int)(idx % kg.nxh);
+        const double2 rh = rho_hat[idx];
+        const double gk = G[idx];
+        const bool edge = (ix == 0) || (2 * ix == kg.K[0]);
+        e += (edge ? 0.5 : 1.0) * gk * (rh.x * rh.x + rh.y * rh.y);
+        const double re = gk * rh.x, im = gk * rh.y;
+        if (mode == 1) {  // ad: potential only
+            store_c(spec + idx, re, im);
+        } else {
+            const int iy = (int)((idx / kg.nxh) % kg.K[1]);
+            const int iz = (int)(idx / ((long long)kg.nxh * kg.K[1]));
+            const int ii[3] = {ix, iy, iz};
+            for (int d = 0; d < 3; ++d) {
+                const int n = (2 * ii[d] == kg.K[d]) ? 0 : fft_index(ii[d], kg.K[d]);
+                const double kap = two_pi * (double)n / kg.len[d];
+                // -i kappa (re + i im) = kappa im - i kappa re
+                store_c(spec + d * nspec + idx, kap * im, -kap * re);
+            }
+        }
+    }
+    for (int d = 32; d > 0; d >>= 1) e += __shfl_down(e, d, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < KSPACE_THREADS / 64; ++w) s += red[w];
+        epart[blockIdx.x] = s;
+    }
+}
+
+// phi_hat only, into the slot after the ik field spectra (adjoint of ik plans).
+template <typename C>
+__global__ __launch_bounds__(KSPACE_THREADS) void k_phi_only(long long nspec, const double2* __restrict__ rho_hat,
+                                                              const double* __restrict__ G, C* __restrict__ out)
+{
+    for (long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x; idx < nspec;
+         idx += (long long)gridDim.x * KSPACE_THREADS) {
+        const double2 rh = rho_hat[idx];
+        const double gk = G[idx];
+        store_c(out + idx, gk * rh.x, gk * rh.y);
+    }
+}
+
+// Deterministic final sums: E_mesh from the k-space partials, Q and sum q^2
+// from the particle-map partials; E_self = -C g / sqrt(pi) sum q^2,
+// E_bg = -C pi Q^2 / (2 V g^2).
+__global__ __launch_bounds__(1024) void k_energy_final(int ne, const double* __restrict__ epart, int nq,
+                                                       const double* __restrict__ qpart, double self_c,
+                                                       double bg_c, double* __restrict__ eterms,
+                                                       double* __restrict__ energy_out)
+{
+    __shared__ double red[3][16];
+    double e = 0.0, qs = 0.0, q2 = 0.0;
+    for (int i = threadIdx.x; i < ne; i += blockDim.x) e += epart[i];
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+        qs += qpart[2 * i];
+        q2 += qpart[2 * i + 1];
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        e += __shfl_down(e, d, 64);
+        qs += __shfl_down(qs, d, 64);
+        q2 += __shfl_down(q2, d, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wid] = e;
+        red[1][wid] = qs;
+        red[2][wid] = q2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double E = 0.0, Q = 0.0, Q2 = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            E += red[0][w];
+            Q += red[1][w];
+            Q2 += red[2][w];
+        }
+        const double e_self = -self_c * Q2;
+        const double e_bg = -bg_c * Q * Q;
+        const double total = E + e_self + e_bg;
+        eterms[0] = total;
+        eterms[1] = E;
+        eterms[2] = e_self;
+        eterms[3] = e_bg;
+        eterms[4] = Q;
+        eterms[5] = Q2;
+        if (energy_out) *energy_out = total;
+    }
+}
+
+KGeo make_kgeo(const pppm_plan_s* pl)
+{
+    KGeo kg{};
+    for (int d = 0; d < 3; ++d) {
+        kg.K[d] = pl->geo.K[d];
+        kg.len[d] = pl->p.box_len[d];
+        kg.h[d] = pl->geo.h[d];
+    }
+    kg.nxh = kg.K[0] / 2 + 1;
+    return kg;
+}
+
+int kspace_blocks(long long nspec)
+{
+    const long long b = (nspec + KSPACE_THREADS - 1) / KSPACE_THREADS;
+    return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+hipError_t launch_influence(pppm_plan_s* pl)
+{
+    const KGeo kg = make_kgeo(pl);
+    const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
+    const long long blocks = (pl->nspec + KSPACE_THREADS - 1) / KSPACE_THREADS;
+    k_influence<<<(unsigned)blocks, KSPACE_THREADS, 0, pl->stream>>>(
+        kg, pl->nspec, pl->p.order, pl->p.g_ewald, (int)pl->p.diff, pl->p.coulomb_c / V, pl->G);
+    return hipGetLastError();
+}
+
+hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only)
+{
+    const KGeo kg = make_kgeo(pl);
+    const int blocks = kspace_blocks(pl->nspec);
+    if (phi_only) {
+        const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
+        void* out = (char*)pl->spec + 3 * pl->nspec * csz;
+        if (pl->mixed)
+            k_phi_only<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(pl->nspec, (const double2*)pl->rho_hat,
+                                                                           pl->G, (float2*)out);
+        else
+            k_phi_only<double2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(pl->nspec, (const double2*)pl->rho_hat,
+                                                                            pl->G, (double2*)out);
+        return hipGetLastError();
+    }
+    pl->epart_blocks = blocks;
+    const int mode = (pl->p.diff == PPPM_DIFF_AD) ? 1 : 0;
+    if (pl->mixed)
+        k_solve<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, mode, (const double2*)pl->rho_hat,
+                                                                    pl->G, (float2*)pl->spec, pl->epart);
+    else
+        k_solve<double2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, mode, (const double2*)pl->rho_hat,
+                                                                     pl->G, (double2*)pl->spec, pl->epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out)
+{
+    const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
+    const double C = pl->p.coulomb_c, g = pl->p.g_ewald;
+    const double self_c = C * g / sqrt(M_PI);
+    const double bg_c = C * M_PI / (2.0 * V * g * g);
+    k_energy_final<<<1, 1024, 0, pl->stream>>>((int)pl->epart_blocks, pl->epart, (int)pl->qpart_blocks, pl->qpart,
+                                               self_c, bg_c, pl->eterms, energy_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3)
+{
+    return hipMemcpyAsync(out3, pl->eterms + 1, 3 * sizeof(double), hipMemcpyDeviceToDevice, pl->stream);
+}
+
+}  // namespace pppm

@@ -1,0 +1,529 @@
+// C ABI of the MI355X PPPM library: parameter validation, plan lifetime,
+// device scratch, rocFFT plans and the enqueue order of the steps
+//   particle map -> make_rho -> Poisson (FFT, G multiply, energy, inverse
+//   FFT) -> fieldforce,
+// following the three-step PPPM evaluation of the paper (Section 2.1) with
+// the per-atom stencil setup of Section 3.1 as its own step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "pppm_internal.h"
+
+using namespace pppm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pppm_status fail(pppm_plan_s* pl, pppm_status st, const std::string& msg)
+{
+    if (pl)
+        pl->last_error = msg;
+    else
+        g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(pl, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((pl), PPPM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FFT_TRY(pl, call)                                                                          \
+    do {                                                                                           \
+        rocfft_status s_ = (call);                                                                 \
+        if (s_ != rocfft_status_success)                                                           \
+            return fail((pl), PPPM_ERR_FFT, std::string(#call) + ": rocfft status " + std::to_string((int)s_)); \
+    } while (0)
+
+constexpr int64_t MAX_CELLS = int64_t(1) << 30;
+constexpr int MAX_MESH = 2048;
+constexpr size_t LDS_BUDGET = 64 * 1024 - 1024;  // dynamic LDS per workgroup
+
+std::once_flag g_fft_once;
+rocfft_status g_fft_setup = rocfft_status_success;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+pppm_status validate(const pppm_params* p, std::string& why)
+{
+    if (!p) {
+        why = "params is NULL";
+        return PPPM_ERR_ARG;
+    }
+    if (p->order < 2 || p->order > 7) {
+        why = "order must be in [2, 7], got " + std::to_string(p->order);
+        return PPPM_ERR_ORDER;
+    }
+    int64_t cells = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (!(std::isfinite(p->box_len[d]) && p->box_len[d] > 0.0) || !std::isfinite(p->box_lo[d])) {
+            why = "box_lo must be finite and box_len positive and finite";
+            return PPPM_ERR_ARG;
+        }
+        const int K = p->mesh[d];
+        if (K < 2 || K < p->order || K > MAX_MESH) {
+            why = "mesh[" + std::to_string(d) + "] = " + std::to_string(K) + " must be in [max(2, order), 2048]";
+            return PPPM_ERR_MESH;
+        }
+        cells *= K;
+    }
+    if (cells > MAX_CELLS) {
+        why = "more than 2^30 mesh points";
+        return PPPM_ERR_MESH;
+    }
+    if (!(std::isfinite(p->g_ewald) && p->g_ewald > 0.0)) {
+        why = "g_ewald must be positive and finite";
+        return PPPM_ERR_ARG;
+    }
+    if (!std::isfinite(p->coulomb_c) || p->coulomb_c == 0.0) {
+        why = "coulomb_c must be finite and non-zero";
+        return PPPM_ERR_ARG;
+    }
+    if (p->diff != PPPM_DIFF_IK && p->diff != PPPM_DIFF_AD) {
+        why = "diff must be PPPM_DIFF_IK or PPPM_DIFF_AD";
+        return PPPM_ERR_ARG;
+    }
+    if (p->prec != PPPM_PREC_FP64 && p->prec != PPPM_PREC_MIXED) {
+        why = "prec must be PPPM_PREC_FP64 or PPPM_PREC_MIXED";
+        return PPPM_ERR_DTYPE;
+    }
+    if (p->io_dtype != PPPM_F32 && p->io_dtype != PPPM_F64) {
+        why = "io_dtype must be PPPM_F32 or PPPM_F64";
+        return PPPM_ERR_DTYPE;
+    }
+    if (p->max_particles < 0 || p->max_particles > 2147483647LL) {
+        why = "max_particles must be in [0, 2^31 - 1]";
+        return PPPM_ERR_ARG;
+    }
+    if (p->flags & ~PPPM_FLAG_CHECK_FINITE) {
+        why = "unknown flag bits";
+        return PPPM_ERR_ARG;
+    }
+    return PPPM_OK;
+}
+
+size_t lds_of(const pppm_plan_s* pl, int which, const LaunchCfg& c)
+{
+    if (which == 0) return spread_lds_bytes(pl, c);
+    return gather_lds_bytes(pl, c, which == 1 ? pl->ncomp : 1);
+}
+
+// Check a launch configuration; returns an empty string if it is usable.
+std::string check_cfg(const pppm_plan_s* pl, int which, const LaunchCfg& c)
+{
+    for (int d = 0; d < 3; ++d)
+        if (!is_pow2(c.tile[d]) || c.tile[d] < SB || c.tile[d] > 64) return "tile edges must be powers of two in [4, 64]";
+    if (c.threads < 64 || c.threads > 512 || c.threads % 64) return "threads must be a multiple of 64 in [64, 512]";
+    const size_t lds = lds_of(pl, which, c);
+    if (lds > LDS_BUDGET || lds > pl->lds_limit) return "tile needs " + std::to_string(lds) + " bytes of LDS";
+    if (runs_needed(pl, c, which == 0) > MAX_RUNS) return "tile reads too many sub-bricks";
+    return "";
+}
+
+// Default geometry: 16^3 tiles (no larger than the mesh), halved along the
+// largest edge until the LDS and run-table limits hold.
+LaunchCfg default_cfg(const pppm_plan_s* pl, int which)
+{
+    LaunchCfg c{};
+    for (int d = 0; d < 3; ++d) {
+        int b = 16;
+        while (b > SB && b / 2 >= pl->geo.K[d]) b /= 2;
+        c.tile[d] = b;
+    }
+    c.threads = 256;
+    for (int it = 0; it < 16 && !check_cfg(pl, which, c).empty(); ++it) {
+        int dm = 0;
+        for (int d = 1; d < 3; ++d)
+            if (c.tile[d] >= c.tile[dm]) dm = d;
+        if (c.tile[dm] <= SB) break;
+        c.tile[dm] /= 2;
+    }
+    return c;
+}
+
+template <typename T>
+pppm_status dmalloc(pppm_plan_s* pl, T** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc((void**)ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(pl, PPPM_ERR_OOM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    return PPPM_OK;
+}
+
+void release(pppm_plan_s* pl)
+{
+    if (pl->fft_fwd) rocfft_plan_destroy(pl->fft_fwd);
+    if (pl->fft_inv) rocfft_plan_destroy(pl->fft_inv);
+    if (pl->fft_inv1) rocfft_plan_destroy(pl->fft_inv1);
+    if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
+    void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart,
+                    pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags,
+                    pl->fft_work};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+pppm_status make_fft_plans(pppm_plan_s* pl)
+{
+    std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
+    FFT_TRY(pl, g_fft_setup);
+    const size_t lengths[3] = {(size_t)pl->geo.K[0], (size_t)pl->geo.K[1], (size_t)pl->geo.K[2]};
+    const rocfft_precision inv_prec = pl->mixed ? rocfft_precision_single : rocfft_precision_double;
+    FFT_TRY(pl, rocfft_plan_create(&pl->fft_fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                                   rocfft_precision_double, 3, lengths, 1, nullptr));
+    FFT_TRY(pl, rocfft_plan_create(&pl->fft_inv, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                                   inv_prec, 3, lengths, (size_t)pl->ncomp, nullptr));
+    if (pl->p.diff == PPPM_DIFF_IK)
+        FFT_TRY(pl, rocfft_plan_create(&pl->fft_inv1, rocfft_placement_notinplace,
+                                       rocfft_transform_type_real_inverse, inv_prec, 3, lengths, 1, nullptr));
+    size_t w = 0, wi = 0;
+    FFT_TRY(pl, rocfft_plan_get_work_buffer_size(pl->fft_fwd, &w));
+    FFT_TRY(pl, rocfft_plan_get_work_buffer_size(pl->fft_inv, &wi));
+    w = w > wi ? w : wi;
+    if (pl->fft_inv1) {
+        FFT_TRY(pl, rocfft_plan_get_work_buffer_size(pl->fft_inv1, &wi));
+        w = w > wi ? w : wi;
+    }
+    FFT_TRY(pl, rocfft_execution_info_create(&pl->fft_info));
+    FFT_TRY(pl, rocfft_execution_info_set_stream(pl->fft_info, pl->stream));
+    if (w > 0) {
+        pppm_status st = dmalloc(pl, &pl->fft_work, w);
+        if (st != PPPM_OK) return st;
+        pl->fft_work_bytes = w;
+        FFT_TRY(pl, rocfft_execution_info_set_work_buffer(pl->fft_info, pl->fft_work, w));
+    }
+    return PPPM_OK;
+}
+
+pppm_status check_plan(pppm_plan_s* pl)
+{
+    if (!pl) return fail(nullptr, PPPM_ERR_ARG, "plan is NULL");
+    pl->last_error.clear();
+    return PPPM_OK;
+}
+
+pppm_status do_particle_map(pppm_plan_s* pl, int64_t n, const void* pos, const void* q)
+{
+    if (n < 0 || n > pl->p.max_particles)
+        return fail(pl, PPPM_ERR_ARG, "n = " + std::to_string(n) + " outside [0, max_particles = " +
+                                          std::to_string(pl->p.max_particles) + "]");
+    if (n > 0 && (!pos || !q)) return fail(pl, PPPM_ERR_ARG, "pos and q must not be NULL");
+    pl->stage = Stage::Empty;
+    pl->phi_valid = false;
+    HIP_TRY(pl, launch_map_count(pl, n, pos, q));
+    HIP_TRY(pl, launch_scan(pl));
+    HIP_TRY(pl, launch_scatter(pl, n, pos, q));
+    pl->n = n;
+    pl->pos_ptr = pos;
+    pl->q_ptr = q;
+    pl->stage = Stage::Mapped;
+    return PPPM_OK;
+}
+
+pppm_status do_make_rho(pppm_plan_s* pl, double* rho)
+{
+    if (pl->stage < Stage::Mapped) return fail(pl, PPPM_ERR_STATE, "make_rho before particle_map");
+    HIP_TRY(pl, launch_spread(pl, rho));
+    pl->stage = Stage::Spread;
+    pl->phi_valid = false;
+    return PPPM_OK;
+}
+
+pppm_status do_poisson(pppm_plan_s* pl, double* energy)
+{
+    if (pl->stage < Stage::Spread) return fail(pl, PPPM_ERR_STATE, "poisson before make_rho");
+    void* in[1] = {pl->rho};
+    void* out[1] = {pl->rho_hat};
+    FFT_TRY(pl, rocfft_execute(pl->fft_fwd, in, out, pl->fft_info));
+    HIP_TRY(pl, launch_kspace(pl, false));
+    HIP_TRY(pl, launch_energy_final(pl, energy));
+    void* sin_[1] = {pl->spec};
+    void* fout[1] = {pl->field};
+    FFT_TRY(pl, rocfft_execute(pl->fft_inv, sin_, fout, pl->fft_info));
+    HIP_TRY(pl, hipGetLastError());
+    pl->stage = Stage::Solved;
+    pl->phi_valid = (pl->p.diff == PPPM_DIFF_AD);
+    return PPPM_OK;
+}
+
+pppm_status do_fieldforce(pppm_plan_s* pl, void* forces)
+{
+    if (pl->stage < Stage::Solved) return fail(pl, PPPM_ERR_STATE, "fieldforce before poisson");
+    if (!forces) return fail(pl, PPPM_ERR_ARG, "forces is NULL");
+    if (pl->n == 0) return PPPM_OK;
+    HIP_TRY(pl, launch_gather(pl, pl->p.diff == PPPM_DIFF_IK ? GATHER_IK : GATHER_AD, forces, nullptr, nullptr));
+    return PPPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pppm_status pppm_validate(const pppm_params* params)
+{
+    std::string why;
+    pppm_status st = validate(params, why);
+    if (st != PPPM_OK) return fail(nullptr, st, why);
+    return PPPM_OK;
+}
+
+pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_plan* out)
+{
+    if (!out) return fail(nullptr, PPPM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    pppm_status st = validate(params, why);
+    if (st != PPPM_OK) return fail(nullptr, st, why);
+
+    auto* pl = new pppm_plan_s();
+    pl->p = *params;
+    pl->stream = (hipStream_t)hip_stream;
+    pl->mixed = params->prec == PPPM_PREC_MIXED;
+    pl->rsize = pl->mixed ? sizeof(float) : sizeof(double);
+    pl->ncomp = params->diff == PPPM_DIFF_IK ? 3 : 1;
+
+    auto bail = [&](pppm_status s) {
+        g_last_error = pl->last_error;
+        release(pl);
+        delete pl;
+        return s;
+    };
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e != hipSuccess) {
+        pl->last_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return bail(PPPM_ERR_HIP);
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, pl->device);
+    if (e != hipSuccess) {
+        pl->last_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+        return bail(PPPM_ERR_HIP);
+    }
+    pl->lds_limit = prop.sharedMemPerBlock;
+
+    MapGeo& g = pl->geo;
+    for (int d = 0; d < 3; ++d) {
+        g.lo[d] = params->box_lo[d];
+        g.K[d] = params->mesh[d];
+        g.h[d] = params->box_len[d] / (double)params->mesh[d];
+        g.nsb[d] = (g.K[d] + SB - 1) / SB;
+    }
+    g.shift = 1.0 - 0.5 * params->order;
+    g.check_finite = (params->flags & PPPM_FLAG_CHECK_FINITE) ? 1 : 0;
+    pl->ncell = (int64_t)g.K[0] * g.K[1] * g.K[2];
+    pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
+    pl->nsub = (int64_t)g.nsb[0] * g.nsb[1] * g.nsb[2];
+
+    const int64_t nmax = params->max_particles;
+    const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
+    const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
+    const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
+    const int64_t scan_blocks = (pl->nsub + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if ((st = dmalloc(pl, &pl->count, pl->nsub * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->offsets, (pl->nsub + 1) * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->scan_part, scan_blocks * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->qpart, 2 * map_blocks * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho, pl->ncell * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho_hat, pl->nspec * sizeof(double2))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->nspec * csz)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->field, (pl->ncomp + 1) * pl->ncell * pl->rsize)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->G, pl->nspec * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->epart, 2048 * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
+        return bail(st);
+
+    e = hipMemsetAsync(pl->count, 0, pl->nsub * sizeof(int), pl->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 8 * sizeof(double), pl->stream);
+    if (e != hipSuccess) {
+        pl->last_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+        return bail(PPPM_ERR_HIP);
+    }
+    e = launch_influence(pl);
+    if (e != hipSuccess) {
+        pl->last_error = std::string("influence function: ") + hipGetErrorString(e);
+        return bail(PPPM_ERR_HIP);
+    }
+    if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
+
+    pl->spread_cfg = default_cfg(pl, 0);
+    pl->gather_cfg = default_cfg(pl, 1);
+    pl->adjoint_cfg = default_cfg(pl, 2);
+    for (int w = 0; w < 3; ++w) {
+        const LaunchCfg& c = w == 0 ? pl->spread_cfg : (w == 1 ? pl->gather_cfg : pl->adjoint_cfg);
+        std::string bad = check_cfg(pl, w, c);
+        if (!bad.empty()) {
+            pl->last_error = "no usable launch geometry: " + bad;
+            return bail(PPPM_ERR_MESH);
+        }
+    }
+    e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) {
+        pl->last_error = std::string("plan setup: ") + hipGetErrorString(e);
+        return bail(PPPM_ERR_HIP);
+    }
+    *out = pl;
+    return PPPM_OK;
+}
+
+pppm_status pppm_plan_destroy(pppm_plan plan)
+{
+    if (!plan) return PPPM_OK;
+    (void)hipStreamSynchronize(plan->stream);
+    release(plan);
+    delete plan;
+    return PPPM_OK;
+}
+
+pppm_status pppm_particle_map(pppm_plan plan, int64_t n, const void* pos, const void* q)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    return do_particle_map(plan, n, pos, q);
+}
+
+pppm_status pppm_make_rho(pppm_plan plan, double* rho)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    return do_make_rho(plan, rho);
+}
+
+pppm_status pppm_poisson(pppm_plan plan, double* energy)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    return do_poisson(plan, energy);
+}
+
+pppm_status pppm_fieldforce(pppm_plan plan, void* forces)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    return do_fieldforce(plan, forces);
+}
+
+pppm_status pppm_compute(pppm_plan plan, int64_t n, const void* pos, const void* q, double* rho, double* energy,
+                         void* forces)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    if ((st = do_particle_map(plan, n, pos, q)) != PPPM_OK) return st;
+    if ((st = do_make_rho(plan, rho)) != PPPM_OK) return st;
+    if ((st = do_poisson(plan, energy)) != PPPM_OK) return st;
+    if (forces) return do_fieldforce(plan, forces);
+    return PPPM_OK;
+}
+
+pppm_status pppm_energy_backward(pppm_plan plan, const double* grad_energy, int64_t n, const void* pos,
+                                 const void* q, void* grad_pos, void* grad_q)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    pppm_plan_s* pl = plan;
+    if (!grad_energy) return fail(pl, PPPM_ERR_ARG, "grad_energy is NULL");
+    if (pl->stage < Stage::Solved || n != pl->n || pos != pl->pos_ptr || q != pl->q_ptr)
+        return fail(pl, PPPM_ERR_STATE, "energy_backward needs a preceding compute on the same pos, q and n");
+    if (n == 0 || (!grad_pos && !grad_q)) return PPPM_OK;
+    const bool phi_valid = pl->phi_valid;
+    // re-derive the binned records and stencils from the positions
+    if ((st = do_particle_map(pl, n, pos, q)) != PPPM_OK) return st;
+    pl->stage = Stage::Solved;
+    pl->phi_valid = phi_valid;
+    if (!pl->phi_valid) {
+        // ik plan: the potential mesh of the same influence function
+        HIP_TRY(pl, launch_kspace(pl, true));
+        const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
+        void* sin_[1] = {(char*)pl->spec + 3 * pl->nspec * csz};
+        void* fout[1] = {(char*)pl->field + 3 * pl->ncell * pl->rsize};
+        FFT_TRY(pl, rocfft_execute(pl->fft_inv1, sin_, fout, pl->fft_info));
+        pl->phi_valid = true;
+    }
+    HIP_TRY(pl, launch_gather(pl, GATHER_ADJOINT, grad_pos, grad_q, grad_energy));
+    return PPPM_OK;
+}
+
+pppm_status pppm_energy_terms(pppm_plan plan, double* out3)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    if (!out3) return fail(plan, PPPM_ERR_ARG, "out3 is NULL");
+    HIP_TRY(plan, launch_copy_terms(plan, out3));
+    return PPPM_OK;
+}
+
+pppm_status pppm_sync(pppm_plan plan)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    HIP_TRY(plan, hipStreamSynchronize(plan->stream));
+    int flag = 0;
+    HIP_TRY(plan, hipMemcpy(&flag, plan->flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        HIP_TRY(plan, hipMemset(plan->flags, 0, sizeof(int)));
+        return fail(plan, PPPM_ERR_NONFINITE, "a position or charge was not finite");
+    }
+    return PPPM_OK;
+}
+
+const char* pppm_status_string(pppm_status status)
+{
+    switch (status) {
+    case PPPM_OK: return "PPPM_OK";
+    case PPPM_ERR_ARG: return "PPPM_ERR_ARG: invalid argument";
+    case PPPM_ERR_ORDER: return "PPPM_ERR_ORDER: order outside [2, 7]";
+    case PPPM_ERR_MESH: return "PPPM_ERR_MESH: invalid mesh";
+    case PPPM_ERR_DTYPE: return "PPPM_ERR_DTYPE: invalid precision or dtype";
+    case PPPM_ERR_NONFINITE: return "PPPM_ERR_NONFINITE: non-finite input";
+    case PPPM_ERR_OOM: return "PPPM_ERR_OOM: device allocation failed";
+    case PPPM_ERR_HIP: return "PPPM_ERR_HIP: HIP runtime error";
+    case PPPM_ERR_FFT: return "PPPM_ERR_FFT: rocFFT error";
+    case PPPM_ERR_STATE: return "PPPM_ERR_STATE: call out of order";
+    }
+    return "unknown pppm_status";
+}
+
+const char* pppm_last_error(pppm_plan plan)
+{
+    return plan ? plan->last_error.c_str() : g_last_error.c_str();
+}
+
+pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t* tile, int32_t threads)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    if (which < 0 || which > 2 || !tile) return fail(plan, PPPM_ERR_ARG, "which must be 0, 1 or 2 and tile non-NULL");
+    LaunchCfg c{{tile[0], tile[1], tile[2]}, threads};
+    std::string bad = check_cfg(plan, which, c);
+    if (!bad.empty()) return fail(plan, PPPM_ERR_ARG, bad);
+    (which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg)) = c;
+    return PPPM_OK;
+}
+
+pppm_status pppm_plan_get_launch(pppm_plan plan, int32_t which, int32_t* tile, int32_t* threads)
+{
+    pppm_status st = check_plan(plan);
+    if (st != PPPM_OK) return st;
+    if (which < 0 || which > 2 || !tile || !threads) return fail(plan, PPPM_ERR_ARG, "bad arguments");
+    const LaunchCfg& c = which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg);
+    for (int d = 0; d < 3; ++d) tile[d] = c.tile[d];
+    *threads = c.threads;
+    return PPPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations of the MI355X PPPM library: plan state, launch
+// geometry and the host launchers of the HIP kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pppm.h"
+
+namespace pppm {
+
+// Particles are binned by the mesh sub-brick (SB^3 points) holding their
+// stencil start.  Workgroup tiles are multiples of it.
+constexpr int SB = 4;
+constexpr int MAP_THREADS = 256;
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 4;  // counts per thread per scan block
+constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_ITEMS;
+constexpr int KSPACE_THREADS = 256;
+constexpr int MAX_RUNS = 1024;  // sub-bricks a workgroup may read
+
+// Geometry shared by the particle-side kernels (passed by value).
+struct MapGeo {
+    double lo[3];
+    double h[3];      // L / K, the same double the host computes
+    double shift;     // 1 - P/2: stencil start s = floor(u + shift)
+    int K[3];
+    int nsb[3];       // sub-bricks per axis, ceil(K / SB)
+    int check_finite;
+};
+
+// Workgroup tile decomposition of the mesh.
+struct TileGeo {
+    int K[3];
+    int nsb[3];
+    int B[3];         // tile edge in mesh points (multiple of SB)
+    int ntile[3];     // tiles per axis, ceil(K / B)
+    int ntiles;
+};
+
+struct LaunchCfg {
+    int tile[3];
+    int threads;
+};
+
+enum class Stage { Empty = 0, Mapped = 1, Spread = 2, Solved = 3 };
+
+}  // namespace pppm
+
+struct pppm_plan_s {
+    pppm_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t lds_limit = 65536;
+
+    pppm::MapGeo geo{};
+    int64_t ncell = 0;   // Kx Ky Kz
+    int64_t nspec = 0;   // Kz Ky (Kx/2 + 1): half spectrum of a real transform
+    int64_t nsub = 0;    // sub-bricks
+    int ncomp = 1;       // field meshes of the forward gather: 3 (ik) or 1 (ad)
+    bool mixed = true;
+    size_t rsize = 4;    // bytes of the particle-side real type (float / double)
+
+    // device buffers owned by the plan
+    int* count = nullptr;      // [nsub] particles per sub-brick (kept zero between calls)
+    int* offsets = nullptr;    // [nsub + 1] exclusive prefix of count
+    int* scan_part = nullptr;  // [ceil(nsub / SCAN_BLOCK)] block sums of count
+    int* slot = nullptr;       // [max_particles] rank of a particle within its sub-brick
+    void* records = nullptr;   // [max_particles] float4 / double4 (t_x, t_y, t_z, q) in binned order
+    int* perm = nullptr;       // [max_particles] binned position -> caller index
+    double* qpart = nullptr;   // [2 * map blocks] partial sums of q and q^2
+    double* rho = nullptr;     // [ncell] mesh charge, FFT input
+    void* rho_hat = nullptr;   // [nspec] complex double
+    void* spec = nullptr;      // [(ncomp + 1) * nspec] complex R: field spectra, then phi spectrum
+    void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
+    double* G = nullptr;       // [nspec] (C / V) G(k)
+    double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
+    double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2
+    int* flags = nullptr;      // [1] sticky non-finite flag
+    void* fft_work = nullptr;
+    size_t fft_work_bytes = 0;
+    int64_t qpart_blocks = 0;
+    int64_t epart_blocks = 0;
+
+    rocfft_plan fft_fwd = nullptr;   // D2Z of rho
+    rocfft_plan fft_inv = nullptr;   // C2R batch ncomp
+    rocfft_plan fft_inv1 = nullptr;  // C2R batch 1 (phi of an ik plan)
+    rocfft_execution_info fft_info = nullptr;
+
+    // launch geometry
+    pppm::LaunchCfg spread_cfg{}, gather_cfg{}, adjoint_cfg{};
+
+    // state
+    pppm::Stage stage = pppm::Stage::Empty;
+    int64_t n = 0;
+    const void* pos_ptr = nullptr;
+    const void* q_ptr = nullptr;
+    bool phi_valid = false;  // field buffer holds phi for the adjoint
+
+    std::string last_error;
+};
+
+namespace pppm {
+
+// ---- host launchers (each returns hipGetLastError() of its launches) ----
+hipError_t launch_map_count(pppm_plan_s* pl, int64_t n, const void* pos, const void* q);
+hipError_t launch_scan(pppm_plan_s* pl);
+hipError_t launch_scatter(pppm_plan_s* pl, int64_t n, const void* pos, const void* q);
+hipError_t launch_spread(pppm_plan_s* pl, double* rho_user);
+hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy);
+hipError_t launch_influence(pppm_plan_s* pl);
+hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only);
+hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out);
+hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);
+
+// LDS bytes a kernel needs for a tile (so the host can validate a launch).
+size_t spread_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c);
+size_t gather_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c, int ncomp);
+TileGeo make_tiles(const pppm_plan_s* pl, const LaunchCfg& c);
+int runs_needed(const pppm_plan_s* pl, const LaunchCfg& c, bool spread);
+
+enum GatherMode { GATHER_IK = 0, GATHER_AD = 1, GATHER_ADJOINT = 2 };
+
+}  // namespace pppm

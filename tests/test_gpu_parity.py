@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element.  Tolerances: mesh charge max-relative
+1e-6 (FP64) / 1e-4 (mixed), forces RMS-relative 1e-5 / 1e-3, energy relative
+1e-6 / 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, rho_err, rms_rel
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1702_04250_amd as pkg  # noqa: E402
+
+PRECS = [("fp64", torch.float64), ("mixed", torch.float32), ("mixed", torch.float64), ("fp64", torch.float32)]
+
+
+def run_and_check(pos, q, box_lo, box_len, mesh, P, g, C, diff, prec, io, launch=None, G=None, label=""):
+    pos_r, q_r = io_round(pos, q, io)
+    plan = make_plan(pkg, box_lo, box_len, mesh, P, g, C, diff, prec, io, len(q))
+    if launch:
+        for which, (tile, thr) in launch.items():
+            plan.set_launch(which, tile, thr)
+    print(f"case {label} n={len(q)} mesh={mesh} P={P} {diff} {prec} io={io}", flush=True)
+    gpu = gpu_run(plan, pos_r, q_r, io)
+    ref = oracle_run(pos_r, q_r, box_lo, box_len, mesh, P, g, C, diff, G=G)
+    errs, bad = compare(gpu, ref, prec)
+    print(f"  errors {errs}", flush=True)
+    assert not bad, f"{label}: {bad}"
+    # energy terms
+    terms = gpu["terms"]
+    t = TOL[prec]["energy"]
+    assert abs(terms[0] - ref["e_mesh"]) <= t * abs(ref["e_mesh"]) + 1e-12
+    assert abs(terms[1] - ref["e_self"]) <= 1e-12 * max(abs(ref["e_self"]), 1) or prec == "mixed"
+    plan.close()
+    return gpu, ref
+
+
+@pytest.mark.parametrize("prec,io", PRECS)
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_config1(diff, prec, io):
+    w = W.config(1)
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C1")
+
+
+@pytest.mark.parametrize("prec,io", [("fp64", torch.float64), ("mixed", torch.float32)])
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_config2_water(diff, prec, io):
+    w = W.config(2)
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C2")
+
+
+@pytest.mark.parametrize("P", [3, 4, 5, 6, 7])
+def test_config3_order_sweep_ad_mixed(P):
+    w = W.config(3, order=P)
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                  label=f"C3 P={P}")
+
+
+@pytest.mark.parametrize("diff,prec,io", [("ik", "mixed", torch.float32), ("ad", "fp64", torch.float64),
+                                          ("ik", "fp64", torch.float64)])
+def test_config3_p5_other_forms(diff, prec, io):
+    w = W.config(3)
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, diff, prec, io, label="C3 P=5")
+
+
+# ---- edge cases --------------------------------------------------------------
+
+EDGE_BOX = ((-3.0, 2.0, 0.5), (11.0, 13.0, 7.5))
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("mesh", [(18, 20, 13), (7, 9, 11), (32, 8, 24)])
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_ragged_meshes_and_orders(P, mesh, diff):
+    if min(mesh) < P:
+        pytest.skip("mesh smaller than the order")
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(257, length, seed=P * 100 + mesh[0], box_lo=lo)
+    run_and_check(pos, q, lo, length, mesh, P, 0.45, 1.7, diff, "fp64", torch.float64, label="ragged")
+
+
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_minimum_mesh_equal_to_order(diff):
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(50, length, seed=3, box_lo=lo)
+    run_and_check(pos, q, lo, length, (5, 5, 5), 5, 0.6, 1.0, diff, "fp64", torch.float64, label="K=P")
+    run_and_check(pos, q, lo, length, (2, 3, 2), 2, 0.6, 1.0, diff, "fp64", torch.float64, label="K=2")
+
+
+@pytest.mark.parametrize("prec,io", [("fp64", torch.float64), ("mixed", torch.float32)])
+def test_positions_outside_box_and_on_faces(prec, io):
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(400, length, seed=11, box_lo=lo)
+    L = np.asarray(length)
+    pos[:50] += 3 * L          # far images
+    pos[50:100] -= 2 * L
+    pos[100:110] = np.asarray(lo)            # lower corner
+    pos[110:120] = np.asarray(lo) + L        # upper faces == lower faces
+    pos[120:130, 0] = lo[0] + L[0] * (1 - 1e-16)
+    q[130:140] = 0.0                          # zero charges
+    run_and_check(pos, q, lo, length, (16, 16, 12), 5, 0.45, 1.0, "ad", prec, io, label="faces")
+
+
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_single_particle_and_empty(diff):
+    lo, length = EDGE_BOX
+    dev = torch.device("cuda:0")
+    pos = np.array([[0.3, 4.1, 2.2]])
+    q = np.array([1.5])
+    plan = make_plan(pkg, lo, length, (12, 12, 12), 5, 0.5, 1.0, diff, "fp64", torch.float64, 1)
+    gpu = gpu_run(plan, pos, q, torch.float64)
+    ref = oracle_run(pos, q, lo, length, (12, 12, 12), 5, 0.5, 1.0, diff)
+    assert rho_err(gpu["rho"], ref["rho"]) < 1e-12
+    assert abs(gpu["energy"] - ref["energy"]) < 1e-12 * abs(ref["energy"])
+    if diff == "ik":
+        # one charge: momentum conservation makes its ik mesh force vanish
+        assert np.abs(gpu["forces"]).max() < 1e-12 and np.abs(ref["forces"]).max() < 1e-12
+    else:
+        # the ad mesh self-force of a lone charge is small but not zero
+        assert np.abs(ref["forces"]).max() > 1e-8
+        assert rms_rel(gpu["forces"], ref["forces"]) < 1e-9
+    plan.close()
+    # empty system: zero mesh, zero energy; plan with max_particles 0 and n = 0
+    plan = make_plan(pkg, lo, length, (12, 12, 12), 5, 0.5, 1.0, diff, "fp64", torch.float64, 0)
+    out = plan.compute(torch.zeros((0, 3), dtype=torch.float64, device=dev),
+                       torch.zeros((0,), dtype=torch.float64, device=dev), want_rho=True)
+    plan.sync()
+    assert float(out["rho"].abs().max()) == 0.0
+    assert float(out["energy"]) == 0.0
+    assert out["forces"].shape == (0, 3)
+    plan.close()
+
+
+def test_charged_system_background_term():
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(300, length, seed=5, charge="positive", box_lo=lo)
+    gpu, ref = run_and_check(pos, q, lo, length, (16, 16, 12), 5, 0.45, 2.0, "ad", "fp64", torch.float64,
+                             label="charged")
+    assert abs(gpu["terms"][2] - ref["e_bg"]) < 1e-10 * abs(ref["e_bg"])
+
+
+@pytest.mark.parametrize("which,tile,threads", [
+    (0, (8, 8, 8), 128), (0, (16, 8, 4), 64), (0, (32, 16, 8), 512), (0, (4, 4, 4), 256),
+    (1, (8, 8, 8), 128), (1, (16, 16, 4), 512), (1, (4, 8, 16), 64), (1, (32, 8, 8), 256),
+])
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_launch_geometries_agree(which, tile, threads, diff):
+    w = W.config(2)
+    prec, io = "mixed", torch.float32
+    try:
+        run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io,
+                      launch={which: (tile, threads)}, label=f"launch {which} {tile} {threads}")
+    except pkg.PPPMError as e:
+        # a geometry the device cannot hold is refused on the host, never launched
+        assert e.status == -1
+        pytest.skip(str(e))
+
+
+def test_nonfinite_input_flag():
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(100, length, seed=9, box_lo=lo)
+    pos[7, 1] = np.nan
+    pos[8, 0] = np.inf
+    q[9] = np.nan
+    dev = torch.device("cuda:0")
+    plan = make_plan(pkg, lo, length, (12, 12, 12), 5, 0.5, 1.0, "ad", "fp64", torch.float64, 100,
+                     check_finite=True)
+    out = plan.compute(torch.tensor(pos, device=dev), torch.tensor(q, device=dev))
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.sync()
+    assert ei.value.status == -5
+    plan.sync()  # flag cleared
+    # finite inputs afterwards: no flag
+    pos[7, 1] = pos[8, 0] = 0.0
+    q[9] = 0.0
+    plan.compute(torch.tensor(pos, device=dev), torch.tensor(q, device=dev))
+    plan.sync()
+    plan.close()
+
+
+def test_state_errors():
+    lo, length = EDGE_BOX
+    dev = torch.device("cuda:0")
+    plan = make_plan(pkg, lo, length, (12, 12, 12), 5, 0.5, 1.0, "ad", "fp64", torch.float64, 10)
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.make_rho()
+    assert ei.value.status == -9
+    pos = torch.zeros((11, 3), dtype=torch.float64, device=dev)
+    q = torch.zeros((11,), dtype=torch.float64, device=dev)
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.compute(pos, q)
+    assert ei.value.status == -1  # n > max_particles
+    pos, q = pos[:10].contiguous(), q[:10].contiguous()
+    plan.compute(pos, q)
+    ge = torch.ones((), dtype=torch.float64, device=dev)
+    other = pos.clone()
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.energy_backward(ge, other, q)
+    assert ei.value.status == -9
+    plan.sync()
+    plan.close()
+
+
+def test_repeated_calls_are_stable():
+    # the binning counters are reset by each call: same result every time
+    w = W.config(2)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", "fp64", torch.float64, w.n)
+    dev = torch.device("cuda:0")
+    pos, q = torch.tensor(w.pos, device=dev), torch.tensor(w.q, device=dev)
+    first = plan.compute(pos, q, want_rho=True)
+    f0, r0, e0 = first["forces"].clone(), first["rho"].clone(), float(first["energy"])
+    for _ in range(3):
+        out = plan.compute(pos, q, want_rho=True)
+        plan.sync()
+        assert rms_rel(out["forces"].cpu().numpy(), f0.cpu().numpy()) < 1e-13
+        assert rho_err(out["rho"].cpu().numpy(), r0.cpu().numpy()) < 1e-13
+        assert abs(float(out["energy"]) - e0) < 1e-12 * abs(e0)
+    # a smaller system on the same plan
+    out = plan.compute(pos[:1000].contiguous(), q[:1000].contiguous(), want_rho=True)
+    plan.sync()
+    ref = oracle_run(w.pos[:1000], w.q[:1000], w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad")
+    assert rms_rel(out["forces"].cpu().numpy(), ref["forces"]) < 1e-5
+    plan.close()
+
+
+def test_separate_steps_match_compute():
+    w = W.config(2)
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(w.pos, dtype=torch.float32, device=dev)
+    q = torch.tensor(w.q, dtype=torch.float32, device=dev)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ik", "mixed", torch.float32, w.n)
+    a = plan.compute(pos, q, want_rho=True)
+    fa, ra, ea = a["forces"].clone(), a["rho"].clone(), a["energy"].clone()
+    plan.particle_map(pos, q)
+    rho = torch.empty_like(ra)
+    plan.make_rho(rho)
+    e = torch.empty((), dtype=torch.float64, device=dev)
+    plan.poisson(e)
+    f = torch.empty_like(fa)
+    plan.fieldforce(f)
+    plan.sync()
+    assert rms_rel(f.cpu().numpy(), fa.cpu().numpy()) < 1e-6
+    assert rho_err(rho.cpu().numpy(), ra.cpu().numpy()) < 1e-6
+    assert abs(float(e) - float(ea)) < 1e-9 * abs(float(ea))
+    plan.close()
