@@ -1,0 +1,283 @@
+"""Benchmark of the PPPM particle-mesh hot path on one MI355X.
+
+Workload: 524,288 charges (+-1, exactly neutral) uniform in a 170 A cube,
+mesh 128^3, order P = 5, ad differentiation, mixed precision (FP32
+stencils/LDS/gathers, FP64 mesh charge and energy), FP32 particle arrays.
+
+One step = one full forward evaluation through the C ABI: particle map
+(binning), make_rho, Poisson (rocFFT + influence function + FP64 energy),
+fieldforce.  `value` = charges per second over the timed steps.  HIP events
+on the plan's stream give per-kernel times; the roofline entry uses the
+dominant kernel's algorithmic bytes (per charge and per mesh point) over its
+measured time.  Extra fields: the metric's own make_rho + fieldforce rate for
+ad and ik, the FP64 form, the energy backward, errors against the FP64
+oracle, and the oracle itself timed on the host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "particles/s for make_rho+fieldforce (ik & ad) at P=5; % HBM peak; FP32 vs FP64 error"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--order", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the host oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline loop")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kind, n, cells, prec):
+    """Bytes the method must move per launch: particle records once, the mesh
+    once (written by make_rho, read by a gather), forces once."""
+    rec = 16 if prec == "mixed" else 32
+    fmesh = 4 if prec == "mixed" else 8
+    fout = 12 if prec == "mixed" else 24
+    if kind == "make_rho":
+        return n * rec + cells * 8
+    if kind == "fieldforce_ad":
+        return n * (rec + fout) + cells * fmesh
+    if kind == "fieldforce_ik":
+        return n * (rec + fout) + 3 * cells * fmesh
+    if kind == "backward":
+        return n * (rec + fout + fout // 3) + cells * fmesh
+    raise ValueError(kind)
+
+
+class Timer:
+    """Pairs of HIP events on one stream, averaged per label."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+        self.pairs = {}
+
+    def mark(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        return e
+
+    def add(self, label, a, b):
+        self.pairs.setdefault(label, []).append((a, b))
+
+    def mean_us(self, label):
+        return 1e3 * statistics.fmean(a.elapsed_time(b) for a, b in self.pairs[label])
+
+
+def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False):
+    """Warm up, then time exactly `steps` full forward steps (and backward if asked)."""
+    stream = plan.stream
+    dev = plan.device
+    n = pos.shape[0]
+    energy = torch.empty((), dtype=torch.float64, device=dev)
+    forces = torch.empty((n, 3), dtype=pos.dtype, device=dev)
+    ge = torch.ones((), dtype=torch.float64, device=dev)
+
+    def step(timer=None):
+        t = timer
+        e0 = t.mark() if t else None
+        plan.particle_map(pos, q)
+        e1 = t.mark() if t else None
+        plan.make_rho(None)
+        e2 = t.mark() if t else None
+        plan.poisson(energy)
+        e3 = t.mark() if t else None
+        plan.fieldforce(forces)
+        e4 = t.mark() if t else None
+        if backward:
+            plan.energy_backward(ge, pos, q)
+        e5 = t.mark() if t else None
+        if t:
+            t.add("particle_map", e0, e1)
+            t.add("make_rho", e1, e2)
+            t.add("poisson", e2, e3)
+            t.add("fieldforce", e3, e4)
+            if backward:
+                t.add("backward", e4, e5)
+
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        timer = Timer(torch, stream)
+        start = timer.mark()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(timer)
+        end = timer.mark()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    res = {"ms_per_step": total_ms / steps, "wall_ms_per_step": 1e3 * wall / steps}
+    for k in timer.pairs:
+        res[k + "_us"] = timer.mean_us(k)
+    return res, forces, energy
+
+
+def cpu_baseline(w, order, pos_r, q_r, budget_s=12.0):
+    """The FP64 oracle's forward step (make_rho, Poisson, ad gather) on the host."""
+    from oracle import oracle
+
+    box = oracle.Box(w.box_lo, w.box_len, w.mesh, order)
+    G = oracle.influence_function(box, w.g_ewald, "ad")  # setup, untimed
+    times, res = [], None
+    t_start = time.perf_counter()
+    while not times or (time.perf_counter() - t_start < budget_s and len(times) < 5):
+        t0 = time.perf_counter()
+        res = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", G=G)
+        times.append(time.perf_counter() - t0)
+    t = statistics.median(times)
+    return {
+        "value": w.n / t,
+        "unit": "particles/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"full workload ({w.n} charges, mesh {w.mesh[0]}^3, P={order}, ad), "
+                   f"make_rho + numpy-FFT Poisson + ad gather, median of {len(times)} runs, "
+                   "single-threaded C loops and pocketfft; influence function precomputed"),
+        "seconds_per_step": t,
+    }, res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    if args.calib_copy:
+        n = 1 << 28  # 268M floats = 1 GiB
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": 4 * n, "calib_copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    import paper_1702_04250_amd as pkg
+    import workloads
+
+    if not pkg.binding.LIB_PATH.exists():
+        raise SystemExit("libpppm_mi355x.so is not built: run python -m paper_1702_04250_amd.build")
+    order = args.order
+    w = workloads.config(3, order=order)
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(w.pos, dtype=torch.float32, device=dev).contiguous()
+    q = torch.tensor(w.q, dtype=torch.float32, device=dev).contiguous()
+    # the oracle sees exactly the FP32 inputs, promoted to FP64
+    pos_r = pos.cpu().numpy().astype(np.float64)
+    q_r = q.cpu().numpy().astype(np.float64)
+    n, cells = w.n, w.cells
+
+    stream = torch.cuda.Stream(device=dev)
+    plan_ad = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                       max_particles=n, device=dev, stream=stream)
+    head, f_ad, e_ad = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad")
+    plan_ad.sync()
+
+    t_rho, t_ff = head["make_rho_us"], head["fieldforce_us"]
+    b_rho = algorithmic_bytes("make_rho", n, cells, "mixed")
+    b_ff = algorithmic_bytes("fieldforce_ad", n, cells, "mixed")
+    dom, t_dom, b_dom = ("make_rho", t_rho, b_rho) if t_rho >= t_ff else ("fieldforce_ad", t_ff, b_ff)
+    achieved = b_dom / (t_dom * 1e-6) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": n / (head["ms_per_step"] * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}-P{order}: {w.notes}", "n": n, "mesh": list(w.mesh), "order": order,
+                   "diff": "ad", "prec": "mixed (f32 stencils/LDS/gathers, f64 mesh charge, FFT-forward and energy)",
+                   "io_dtype": "f32", "step": "particle_map + make_rho + poisson + fieldforce"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom},
+        "kernels_us": {k[:-3]: v for k, v in head.items() if k.endswith("_us") and k != "wall_ms_per_step"},
+        "make_rho_fieldforce": {
+            "ad": {"us": t_rho + t_ff, "particles_per_s": n / ((t_rho + t_ff) * 1e-6),
+                   "hbm_frac": (b_rho + b_ff) / ((t_rho + t_ff) * 1e-6) / 1e9 / HBM_PEAK_GBS},
+        },
+    }
+    if not args.no_extras:
+        plan_ik = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ik", "mixed", torch.float32,
+                           max_particles=n, device=dev, stream=stream)
+        ik, f_ik, _ = run_loop(torch, plan_ik, pos, q, args.steps, args.warmup, "ik")
+        b_ffik = algorithmic_bytes("fieldforce_ik", n, cells, "mixed")
+        out["make_rho_fieldforce"]["ik"] = {
+            "us": ik["make_rho_us"] + ik["fieldforce_us"],
+            "particles_per_s": n / ((ik["make_rho_us"] + ik["fieldforce_us"]) * 1e-6),
+            "hbm_frac": (b_rho + b_ffik) / ((ik["make_rho_us"] + ik["fieldforce_us"]) * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "ms_per_step": ik["ms_per_step"], "kernels_us": {k[:-3]: v for k, v in ik.items() if k.endswith("_us")},
+        }
+        plan_ik.close()
+        # plain FP64 form on the same GPU (FP64 particle arrays of the same values)
+        pos64, q64 = pos.double(), q.double()
+        plan_64 = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", "fp64", torch.float64,
+                           max_particles=n, device=dev, stream=stream)
+        r64, f_64, e_64 = run_loop(torch, plan_64, pos64, q64, args.steps, args.warmup, "ad")
+        out["fp64_form"] = {"ms_per_step": r64["ms_per_step"], "particles_per_s": n / (r64["ms_per_step"] * 1e-3),
+                            "kernels_us": {k[:-3]: v for k, v in r64.items() if k.endswith("_us")},
+                            "make_rho_fieldforce_particles_per_s":
+                                n / ((r64["make_rho_us"] + r64["fieldforce_us"]) * 1e-6)}
+        # forward + energy backward (autograd form), mixed
+        rb, _, _ = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad", backward=True)
+        out["forward_backward"] = {"ms_per_step": rb["ms_per_step"], "backward_us": rb["backward_us"],
+                                   "particles_per_s": n / (rb["ms_per_step"] * 1e-3)}
+        plan_ad.sync()
+        plan_64.sync()
+        out["_gpu_results"] = (f_ad.cpu().numpy().astype(np.float64), float(e_ad.cpu()),
+                               f_64.cpu().numpy(), float(e_64.cpu()), f_ik.cpu().numpy().astype(np.float64))
+        plan_64.close()
+    plan_ad.close()
+
+    if not args.no_cpu_baseline:
+        base, ref = cpu_baseline(w, order, pos_r, q_r)
+        out["cpu_baseline"] = base
+        if "_gpu_results" in out:
+            fa, ea, f64, e64, _ = out["_gpu_results"]
+
+            def rms(a, b):
+                return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+            out["error_vs_fp64_oracle"] = {
+                "mixed": {"forces_rms_rel": rms(fa, ref["forces"]),
+                          "energy_rel": abs(ea - ref["energy"]) / abs(ref["energy"])},
+                "fp64": {"forces_rms_rel": rms(f64, ref["forces"]),
+                         "energy_rel": abs(e64 - ref["energy"]) / abs(ref["energy"])},
+            }
+    out.pop("_gpu_results", None)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,12 +177,16 @@ const char *pppm_status_string(pppm_status status);
  * pppm_validate / pppm_plan_create on the calling thread. */
 const char *pppm_last_error(pppm_plan plan);
 
-/* Launch geometry of the spread and gather kernels, for tuning.
- * tile[3] = mesh points per workgroup tile along x, y, z (each a power of two
- * in [4, 64], multiple of the 4-point sub-brick); threads = workgroup size
- * (64..512, multiple of 64).  Returns PPPM_ERR_ARG if the shared memory the
- * configuration needs exceeds the device limit.  which: 0 = spread,
- * 1 = gather (forward), 2 = gather (adjoint). */
+/* Launch geometry, for tuning.  tile[3] = mesh points per workgroup tile
+ * along x, y, z (each in [1, 64]; an edge at least the mesh size makes one
+ * tile along that axis); the tile shape is shared by the
+ * binning, spread and gather kernels of the plan, so changing it discards the
+ * mapped particles (call pppm_particle_map or pppm_compute again).  Every
+ * tile must be at least order - 1 points thick along an axis that has more
+ * than one tile.  threads = workgroup size (64..512, multiple of 64) of the
+ * kernel `which`: 0 = spread, 1 = gather (forward), 2 = gather (adjoint).
+ * Returns PPPM_ERR_ARG (and changes nothing) for an unusable geometry,
+ * including one whose shared memory exceeds the device limit. */
 pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t *tile, int32_t threads);
 
 /* Current launch geometry (see pppm_plan_set_launch); host pointers. */

@@ -19,8 +19,8 @@ __device__ __forceinline__ int xcd_remap(int wg, int nwg)
     return x * q + (x < r ? x : r) + local;
 }
 
-// Record of a binned particle: stencil start within its sub-brick plus the
-// fraction (t in [0, SB]) per axis, and the charge.
+// Record of a binned particle: stencil start within its tile plus the
+// fraction (t in [0, B]) per axis, and the charge.
 template <typename R> struct Rec;
 template <> struct Rec<float> { using T = float4; };
 template <> struct Rec<double> { using T = double4; };
@@ -92,22 +92,6 @@ __device__ __forceinline__ void bspline(R f, R (&w)[P], R (&dw)[P])
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) w[j] = a[P - 1 - j];
-}
-
-// Decode one axis of a record: sub-brick sb, local t -> global stencil start
-// s (in [0, K)) and fraction f in [0, 1].  FP32 rounding may push t to the
-// sub-brick edge; clamping keeps s inside the sub-brick the particle was
-// binned in and gives f = 1, which yields the same weights as f = 0 one
-// point further.
-template <typename R>
-__device__ __forceinline__ void decode_axis(R t, int sb, int K, int& s, R& f)
-{
-    const int base = sb * SB;
-    const int lim = min(SB, K - base) - 1;
-    int si = (int)t;
-    si = si < 0 ? 0 : (si > lim ? lim : si);
-    s = base + si;
-    f = t - R(si);
 }
 
 // Inclusive warp-level scan over a 64-wide wavefront.

@@ -16,14 +16,14 @@
 // rows into planes, planes into the result (the "split atom" idea of the ad
 // kernel: the per-atom epilogue is a few register operations).  Results are
 // written straight to the caller's particle order through the permutation.
-#include "runs.h"
+#include "tiles.h"
 
 namespace pppm {
 
 namespace {
 
 struct GatherArgs {
-    TileGeo tg;
+    MapGeo g;
     const int* offsets;
     const void* rec;
     const int* perm;
@@ -46,25 +46,18 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     constexpr int NC = (MODE == GATHER_IK) ? 3 : 1;
     constexpr bool DERIV = (MODE != GATHER_IK);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int lists[3 * MAXL];
-    __shared__ int cnts[3];
-    __shared__ int scratch[17];
-    const TileGeo& tg = a.tg;
+    const MapGeo& g = a.g;
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int tix = tile % tg.ntile[0];
-    const int tiy = (tile / tg.ntile[0]) % tg.ntile[1];
-    const int tiz = tile / (tg.ntile[0] * tg.ntile[1]);
-    const int T0[3] = {tix * tg.B[0], tiy * tg.B[1], tiz * tg.B[2]};
-    const int ext[3] = {min(tg.B[0], tg.K[0] - T0[0]), min(tg.B[1], tg.K[1] - T0[1]),
-                        min(tg.B[2], tg.K[2] - T0[2])};
+    int t[3];
+    tile_coords(g, tile, t);
+    const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
+    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
+    const int first = a.offsets[tile * NCLASS], last = a.offsets[tile * NCLASS + NCLASS];
 
     R* fld = (R*)smem_raw;
     const int plane = a.pitch_x * a.rows_y;
-    const int nsl = plane * (tg.B[2] + P - 1);  // one staged mesh
-    int* run_start = (int*)(fld + NC * nsl);
-    int* run_sb = run_start + MAX_RUNS;
-    int* prefix = run_sb + MAX_RUNS;
+    const int nsl = plane * (g.B[2] + P - 1);  // one staged mesh
 
     // stage tile + upper halo of every field mesh (periodic wrap)
     {
@@ -74,18 +67,16 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const int lx = i % sx, ly = (i / sx) % sy, lz = i / (sx * sy);
             int gx = T0[0] + lx, gy = T0[1] + ly, gz = T0[2] + lz;
-            if (gx >= tg.K[0]) gx -= tg.K[0];
-            if (gy >= tg.K[1]) gy -= tg.K[1];
-            if (gz >= tg.K[2]) gz -= tg.K[2];
-            const size_t g = ((size_t)gz * tg.K[1] + gy) * tg.K[0] + gx;
+            if (gx >= g.K[0]) gx -= g.K[0];
+            if (gy >= g.K[1]) gy -= g.K[1];
+            if (gz >= g.K[2]) gz -= g.K[2];
+            const size_t gi = ((size_t)gz * g.K[1] + gy) * g.K[0] + gx;
             const int li = lz * plane + ly * a.pitch_x + lx;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) fld[c * nsl + li] = fg[c * a.ncell + g];
+            for (int c = 0; c < NC; ++c) fld[c * nsl + li] = fg[c * a.ncell + gi];
         }
     }
-    const int nruns = build_runs(tg, T0, ext, 0, a.offsets, lists, cnts, run_start, prefix, run_sb, scratch);
-    if (nruns < 0) return;
-    const int total = prefix[nruns];
+    __syncthreads();
 
     double gE = 1.0, Q = 0.0;
     if (MODE == GATHER_ADJOINT) {
@@ -95,22 +86,16 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
 
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
-    for (int v = threadIdx.x; v < total; v += blockDim.x) {
-        const int r = find_run(prefix, nruns, v);
-        const int p = run_start[r] + (v - prefix[r]);
+    for (int p = first + threadIdx.x; p < last; p += blockDim.x) {
         const RT pr = rec[p];
-        const int sbp = run_sb[r];
-        const int sbc[3] = {sbp & 1023, (sbp >> 10) & 1023, sbp >> 20};
         const R tt[3] = {pr.x, pr.y, pr.z};
         int l[3];
         R w[3][P], dw[3][P];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            int s;
             R f;
-            decode_axis<R>(tt[d], sbc[d], tg.K[d], s, f);
+            decode_local<R>(tt[d], ext[d], l[d], f);  // own charge: start in [0, ext)
             bspline<P, R, DERIV>(f, w[d], dw[d]);
-            l[d] = s - T0[d];  // own particle: in [0, ext)
         }
         const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
         R o0 = R(0), o1 = R(0), o2 = R(0), o3 = R(0);
@@ -216,15 +201,11 @@ hipError_t dispatch_types(const pppm_plan_s* pl, dim3 grid, dim3 block, size_t l
                  : dispatch_gather<MODE, double, double>(P, grid, block, lds, pl->stream, a);
 }
 
-int gather_pitch(const pppm_plan_s* pl, const LaunchCfg& c) { return c.tile[0] + pl->p.order - 1; }
-
 }  // namespace
 
-size_t gather_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c, int ncomp)
+size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
 {
-    const int P = pl->p.order;
-    const size_t nsl = (size_t)gather_pitch(pl, c) * (c.tile[1] + P - 1) * (c.tile[2] + P - 1);
-    return ncomp * nsl * pl->rsize + 3 * MAX_RUNS * sizeof(int) + sizeof(int);
+    return (size_t)ncomp * (g.B[0] + order - 1) * (g.B[1] + order - 1) * (g.B[2] + order - 1) * elem_bytes;
 }
 
 hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy)
@@ -232,13 +213,13 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     const LaunchCfg& c = (mode == GATHER_ADJOINT) ? pl->adjoint_cfg : pl->gather_cfg;
     const int P = pl->p.order;
     GatherArgs a{};
-    a.tg = make_tiles(pl, c);
+    a.g = pl->geo;
     a.offsets = pl->offsets;
     a.rec = pl->records;
     a.perm = pl->perm;
     a.ncell = pl->ncell;
-    a.pitch_x = gather_pitch(pl, c);
-    a.rows_y = c.tile[1] + P - 1;
+    a.pitch_x = pl->geo.B[0] + P - 1;
+    a.rows_y = pl->geo.B[1] + P - 1;
     for (int d = 0; d < 3; ++d) a.inv_h[d] = 1.0 / pl->geo.h[d];
     a.out0 = out0;
     a.out1 = out1;
@@ -248,18 +229,18 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
     a.bg_coef = pl->p.coulomb_c * M_PI / (V * pl->p.g_ewald * pl->p.g_ewald);
     const size_t rs = pl->rsize;
-    dim3 grid(a.tg.ntiles), block(c.threads);
+    dim3 grid(pl->geo.ntiles), block(c.threads);
     switch (mode) {
     case GATHER_IK:
         a.field = pl->field;
-        return dispatch_types<GATHER_IK>(pl, grid, block, gather_lds_bytes(pl, c, 3), a);
+        return dispatch_types<GATHER_IK>(pl, grid, block, gather_lds_bytes(pl->geo, P, 3, rs), a);
     case GATHER_AD:
         a.field = pl->field;
-        return dispatch_types<GATHER_AD>(pl, grid, block, gather_lds_bytes(pl, c, 1), a);
+        return dispatch_types<GATHER_AD>(pl, grid, block, gather_lds_bytes(pl->geo, P, 1, rs), a);
     default:
-        // phi lives after the ncomp field meshes for ik plans, first for ad plans
+        // phi lives after the three field meshes for ik plans, first for ad plans
         a.field = (const char*)pl->field + (pl->p.diff == PPPM_DIFF_IK ? 3 * pl->ncell * rs : 0);
-        return dispatch_types<GATHER_ADJOINT>(pl, grid, block, gather_lds_bytes(pl, c, 1), a);
+        return dispatch_types<GATHER_ADJOINT>(pl, grid, block, gather_lds_bytes(pl->geo, P, 1, rs), a);
     }
 }
 

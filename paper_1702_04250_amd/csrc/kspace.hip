@@ -148,8 +148,8 @@ __global__ __launch_bounds__(1024) void k_energy_final(int ne, const double* __r
     double e = 0.0, qs = 0.0, q2 = 0.0;
     for (int i = threadIdx.x; i < ne; i += blockDim.x) e += epart[i];
     for (int i = threadIdx.x; i < nq; i += blockDim.x) {
-        qs += qpart[2 * i];
-        q2 += qpart[2 * i + 1];
+        qs += qpart[3 * i];
+        q2 += qpart[3 * i + 1];
     }
     for (int d = 32; d > 0; d >>= 1) {
         e += __shfl_down(e, d, 64);

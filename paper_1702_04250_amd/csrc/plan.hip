@@ -43,12 +43,12 @@ pppm_status fail(pppm_plan_s* pl, pppm_status st, const std::string& msg)
 
 constexpr int64_t MAX_CELLS = int64_t(1) << 30;
 constexpr int MAX_MESH = 2048;
-constexpr size_t LDS_BUDGET = 64 * 1024 - 1024;  // dynamic LDS per workgroup
+constexpr size_t LDS_PREFERRED = 64 * 1024 - 1024;  // keeps several workgroups per CU
+constexpr size_t LDS_STATIC = 1024;                 // static LDS of the kernels, rounded up
 
 std::once_flag g_fft_once;
 rocfft_status g_fft_setup = rocfft_status_success;
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 pppm_status validate(const pppm_params* p, std::string& why)
 {
@@ -108,43 +108,78 @@ pppm_status validate(const pppm_params* p, std::string& why)
     return PPPM_OK;
 }
 
-size_t lds_of(const pppm_plan_s* pl, int which, const LaunchCfg& c)
+// A tile edge B along an axis of K points is usable when the axis is a single
+// tile (B >= K), or when every tile, the last (possibly thinner) one
+// included, is at least P - 1 points thick, so that a stencil only ever
+// reaches into the next tile.
+bool edge_ok(int K, int B, int P)
 {
-    if (which == 0) return spread_lds_bytes(pl, c);
-    return gather_lds_bytes(pl, c, which == 1 ? pl->ncomp : 1);
+    if (B >= K) return true;
+    const int rem = K % B;
+    return B >= P - 1 && (rem == 0 || rem >= P - 1);
 }
 
-// Check a launch configuration; returns an empty string if it is usable.
-std::string check_cfg(const pppm_plan_s* pl, int which, const LaunchCfg& c)
+// Set the plan's tile shape (edges B[3]); returns "" or the reason it is not
+// usable.  Updates the mesh geometry shared by all particle-side kernels.
+std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
 {
-    for (int d = 0; d < 3; ++d)
-        if (!is_pow2(c.tile[d]) || c.tile[d] < SB || c.tile[d] > 64) return "tile edges must be powers of two in [4, 64]";
-    if (c.threads < 64 || c.threads > 512 || c.threads % 64) return "threads must be a multiple of 64 in [64, 512]";
-    const size_t lds = lds_of(pl, which, c);
-    if (lds > LDS_BUDGET || lds > pl->lds_limit) return "tile needs " + std::to_string(lds) + " bytes of LDS";
-    if (runs_needed(pl, c, which == 0) > MAX_RUNS) return "tile reads too many sub-bricks";
+    const int P = pl->p.order;
+    MapGeo g = pl->geo;
+    for (int d = 0; d < 3; ++d) {
+        if (B[d] < 1 || B[d] > 64) return "tile edges must be in [1, 64]";
+        if (!edge_ok(g.K[d], B[d], P))
+            return "tile edge " + std::to_string(B[d]) + " along axis " + std::to_string(d) +
+                   " leaves a tile thinner than order - 1 points";
+        g.B[d] = B[d] < g.K[d] ? B[d] : g.K[d];
+        g.ntile[d] = (g.K[d] + g.B[d] - 1) / g.B[d];
+    }
+    g.ntiles = g.ntile[0] * g.ntile[1] * g.ntile[2];
+    const size_t lds_s = spread_lds_bytes(g, pl->rsize);
+    const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize);
+    const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize);
+    const size_t lim = pl->lds_limit - LDS_STATIC < lds_budget ? pl->lds_limit - LDS_STATIC : lds_budget;
+    if (lds_s > lim || lds_g > lim || lds_a > lim)
+        return "tile needs " + std::to_string(lds_s > lds_g ? lds_s : lds_g) + " bytes of LDS";
+    pl->geo = g;
+    pl->nbins = (int64_t)g.ntiles * NCLASS;
+    pl->stage = Stage::Empty;
     return "";
 }
 
-// Default geometry: 16^3 tiles (no larger than the mesh), halved along the
-// largest edge until the LDS and run-table limits hold.
-LaunchCfg default_cfg(const pppm_plan_s* pl, int which)
+// Edge for an axis of K points near a preferred edge b: split the axis into
+// about K / b equal tiles, fewer if the last one would be thinner than P - 1.
+int split_edge(int K, int b, int P)
 {
-    LaunchCfg c{};
-    for (int d = 0; d < 3; ++d) {
-        int b = 16;
-        while (b > SB && b / 2 >= pl->geo.K[d]) b /= 2;
-        c.tile[d] = b;
+    int n = (K + b / 2) / b;
+    if (n < 1) n = 1;
+    for (; n > 1; --n) {
+        const int B = (K + n - 1) / n;
+        if (B <= 64 && edge_ok(K, B, P)) return B;
     }
-    c.threads = 256;
-    for (int it = 0; it < 16 && !check_cfg(pl, which, c).empty(); ++it) {
-        int dm = 0;
-        for (int d = 1; d < 3; ++d)
-            if (c.tile[d] >= c.tile[dm]) dm = d;
-        if (c.tile[dm] <= SB) break;
-        c.tile[dm] /= 2;
+    return K;  // a single tile
+}
+
+// Default tile: the first usable shape of a preference list (16 x 16 x 8 was
+// fastest on the 128^3 mesh of the benchmark), each axis split evenly.
+std::string default_tile(pppm_plan_s* pl)
+{
+    static const int prefs[][3] = {{16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
+    std::string why;
+    // first within the LDS size that keeps several workgroups per CU, then
+    // anything the device holds (small meshes that cannot be split)
+    for (size_t budget : {LDS_PREFERRED, pl->lds_limit}) {
+        for (const auto& pref : prefs) {
+            int B[3];
+            for (int d = 0; d < 3; ++d) B[d] = split_edge(pl->geo.K[d], pref[d], pl->p.order);
+            if (B[0] > 64 || B[1] > 64 || B[2] > 64) {
+                why = "mesh axis too long for a single tile";
+                continue;
+            }
+            why = set_tile(pl, B, budget);
+            if (why.empty()) return "";
+        }
     }
-    return c;
+    return why;
 }
 
 template <typename T>
@@ -317,26 +352,27 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         g.lo[d] = params->box_lo[d];
         g.K[d] = params->mesh[d];
         g.h[d] = params->box_len[d] / (double)params->mesh[d];
-        g.nsb[d] = (g.K[d] + SB - 1) / SB;
     }
     g.shift = 1.0 - 0.5 * params->order;
+    g.halo = params->order - 1;
     g.check_finite = (params->flags & PPPM_FLAG_CHECK_FINITE) ? 1 : 0;
     pl->ncell = (int64_t)g.K[0] * g.K[1] * g.K[2];
     pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
-    pl->nsub = (int64_t)g.nsb[0] * g.nsb[1] * g.nsb[2];
+    // bins sized for the finest allowed tiling (edges of 4 points)
+    const int64_t max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
 
     const int64_t nmax = params->max_particles;
     const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
     const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
     const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
-    const int64_t scan_blocks = (pl->nsub + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    if ((st = dmalloc(pl, &pl->count, pl->nsub * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->offsets, (pl->nsub + 1) * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->scan_part, scan_blocks * sizeof(int))) != PPPM_OK ||
+    const int64_t scan_blocks = (max_bins + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if ((st = dmalloc(pl, &pl->count, max_bins * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->offsets, (max_bins + 1) * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->scan_part, 2 * scan_blocks * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->qpart, 2 * map_blocks * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->qpart, 3 * map_blocks * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->rho, pl->ncell * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->rho_hat, pl->nspec * sizeof(double2))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->nspec * csz)) != PPPM_OK ||
@@ -347,7 +383,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
 
-    e = hipMemsetAsync(pl->count, 0, pl->nsub * sizeof(int), pl->stream);
+    e = hipMemsetAsync(pl->count, 0, max_bins * sizeof(int), pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 8 * sizeof(double), pl->stream);
     if (e != hipSuccess) {
@@ -361,14 +397,11 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     }
     if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
 
-    pl->spread_cfg = default_cfg(pl, 0);
-    pl->gather_cfg = default_cfg(pl, 1);
-    pl->adjoint_cfg = default_cfg(pl, 2);
-    for (int w = 0; w < 3; ++w) {
-        const LaunchCfg& c = w == 0 ? pl->spread_cfg : (w == 1 ? pl->gather_cfg : pl->adjoint_cfg);
-        std::string bad = check_cfg(pl, w, c);
+    pl->spread_cfg.threads = pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;
+    {
+        std::string bad = default_tile(pl);
         if (!bad.empty()) {
-            pl->last_error = "no usable launch geometry: " + bad;
+            pl->last_error = "no usable tile shape: " + bad;
             return bail(PPPM_ERR_MESH);
         }
     }
@@ -508,10 +541,22 @@ pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t* t
     pppm_status st = check_plan(plan);
     if (st != PPPM_OK) return st;
     if (which < 0 || which > 2 || !tile) return fail(plan, PPPM_ERR_ARG, "which must be 0, 1 or 2 and tile non-NULL");
-    LaunchCfg c{{tile[0], tile[1], tile[2]}, threads};
-    std::string bad = check_cfg(plan, which, c);
-    if (!bad.empty()) return fail(plan, PPPM_ERR_ARG, bad);
-    (which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg)) = c;
+    if (threads < 64 || threads > 512 || threads % 64)
+        return fail(plan, PPPM_ERR_ARG, "threads must be a multiple of 64 in [64, 512]");
+    const MapGeo keep = plan->geo;
+    const int64_t keep_bins = plan->nbins;
+    const Stage keep_stage = plan->stage;
+    if (tile[0] != keep.B[0] || tile[1] != keep.B[1] || tile[2] != keep.B[2]) {
+        const int B[3] = {tile[0], tile[1], tile[2]};
+        std::string bad = set_tile(plan, B, plan->lds_limit);
+        if (!bad.empty()) {
+            plan->geo = keep;
+            plan->nbins = keep_bins;
+            plan->stage = keep_stage;
+            return fail(plan, PPPM_ERR_ARG, bad);
+        }
+    }
+    (which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg)).threads = threads;
     return PPPM_OK;
 }
 
@@ -521,7 +566,7 @@ pppm_status pppm_plan_get_launch(pppm_plan plan, int32_t which, int32_t* tile, i
     if (st != PPPM_OK) return st;
     if (which < 0 || which > 2 || !tile || !threads) return fail(plan, PPPM_ERR_ARG, "bad arguments");
     const LaunchCfg& c = which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg);
-    for (int d = 0; d < 3; ++d) tile[d] = c.tile[d];
+    for (int d = 0; d < 3; ++d) tile[d] = plan->geo.B[d];
     *threads = c.threads;
     return PPPM_OK;
 }

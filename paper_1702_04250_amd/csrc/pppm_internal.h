@@ -12,15 +12,17 @@
 
 namespace pppm {
 
-// Particles are binned by the mesh sub-brick (SB^3 points) holding their
-// stencil start.  Workgroup tiles are multiples of it.
-constexpr int SB = 4;
+// Charges are binned by the workgroup tile (a box of at most B_x x B_y x B_z
+// mesh points) that holds their stencil start, and within a tile by a halo class:
+// bit d is set when the stencil start lies within P - 1 points of the tile's
+// upper face along d, i.e. when the stencil reaches into the next tile along
+// d.  Each tile thus owns 8 consecutive bins.
+constexpr int NCLASS = 8;
 constexpr int MAP_THREADS = 256;
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 4;  // counts per thread per scan block
 constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_ITEMS;
 constexpr int KSPACE_THREADS = 256;
-constexpr int MAX_RUNS = 1024;  // sub-bricks a workgroup may read
 
 // Geometry shared by the particle-side kernels (passed by value).
 struct MapGeo {
@@ -28,21 +30,14 @@ struct MapGeo {
     double h[3];      // L / K, the same double the host computes
     double shift;     // 1 - P/2: stencil start s = floor(u + shift)
     int K[3];
-    int nsb[3];       // sub-bricks per axis, ceil(K / SB)
+    int B[3];         // tile edge in mesh points; the last tile of an axis may be thinner
+    int ntile[3];     // tiles per axis, ceil(K / B)
+    int ntiles;
+    int halo;         // P - 1
     int check_finite;
 };
 
-// Workgroup tile decomposition of the mesh.
-struct TileGeo {
-    int K[3];
-    int nsb[3];
-    int B[3];         // tile edge in mesh points (multiple of SB)
-    int ntile[3];     // tiles per axis, ceil(K / B)
-    int ntiles;
-};
-
 struct LaunchCfg {
-    int tile[3];
     int threads;
 };
 
@@ -59,26 +54,27 @@ struct pppm_plan_s {
     pppm::MapGeo geo{};
     int64_t ncell = 0;   // Kx Ky Kz
     int64_t nspec = 0;   // Kz Ky (Kx/2 + 1): half spectrum of a real transform
-    int64_t nsub = 0;    // sub-bricks
+    int64_t nbins = 0;   // tiles x NCLASS
     int ncomp = 1;       // field meshes of the forward gather: 3 (ik) or 1 (ad)
     bool mixed = true;
     size_t rsize = 4;    // bytes of the particle-side real type (float / double)
 
     // device buffers owned by the plan
-    int* count = nullptr;      // [nsub] particles per sub-brick (kept zero between calls)
-    int* offsets = nullptr;    // [nsub + 1] exclusive prefix of count
-    int* scan_part = nullptr;  // [ceil(nsub / SCAN_BLOCK)] block sums of count
-    int* slot = nullptr;       // [max_particles] rank of a particle within its sub-brick
-    void* records = nullptr;   // [max_particles] float4 / double4 (t_x, t_y, t_z, q) in binned order
+    int* count = nullptr;      // [nbins] charges per bin (kept zero between calls)
+    int* offsets = nullptr;    // [nbins + 1] exclusive prefix of count
+    int* scan_part = nullptr;  // [2 * ceil(nbins / SCAN_BLOCK)] chunk sums, then chunk maxima of count
+    int* slot = nullptr;       // [max_particles] rank of a particle within its bin
+    void* records = nullptr;   // [max_particles] float4 / double4 (t_x, t_y, t_z, q) in binned order;
+                               // t = stencil start within the tile + fraction
     int* perm = nullptr;       // [max_particles] binned position -> caller index
-    double* qpart = nullptr;   // [2 * map blocks] partial sums of q and q^2
+    double* qpart = nullptr;   // [3 * map blocks] per block: sum q, sum q^2, max |q|
     double* rho = nullptr;     // [ncell] mesh charge, FFT input
     void* rho_hat = nullptr;   // [nspec] complex double
     void* spec = nullptr;      // [(ncomp + 1) * nspec] complex R: field spectra, then phi spectrum
     void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
     double* G = nullptr;       // [nspec] (C / V) G(k)
     double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
-    double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2
+    double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, max count, max |q|
     int* flags = nullptr;      // [1] sticky non-finite flag
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;
@@ -116,11 +112,9 @@ hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only);
 hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out);
 hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);
 
-// LDS bytes a kernel needs for a tile (so the host can validate a launch).
-size_t spread_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c);
-size_t gather_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c, int ncomp);
-TileGeo make_tiles(const pppm_plan_s* pl, const LaunchCfg& c);
-int runs_needed(const pppm_plan_s* pl, const LaunchCfg& c, bool spread);
+// LDS bytes a kernel needs for the plan's tile shape.
+size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes);
+size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 
 enum GatherMode { GATHER_IK = 0, GATHER_AD = 1, GATHER_ADJOINT = 2 };
 

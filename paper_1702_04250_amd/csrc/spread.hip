@@ -11,58 +11,95 @@
 // This is the GPU counterpart of the paper's per-thread private grids
 // ("rethread"): privatise, accumulate, then combine - here the combine is a
 // disjoint ownership of the output.
-#include "runs.h"
+//
+// Accumulator.  On gfx950 the LDS float atomic add (ds_add_f32) is processed
+// at about one lane every three clocks for any non-uniform address pattern,
+// some 30x slower than the integer one (ds_add_u32).  The mixed-precision
+// form therefore accumulates each tile in exact 32-bit fixed point: every
+// FP32 contribution q wx wy wz is rounded to an integer multiple of 2^-e and
+// added with ds_add_u32.  Integer addition is associative (modulo 2^32), so
+// the sum is exact and independent of the order of the atomics, and it is
+// correct whenever the final value fits, |rho_m| 2^e < 2^31.  e is chosen per
+// tile from a bound on any of its points: each charge read by the tile adds
+// at most max|q| wmax(P)^3 to a point, with one bit of headroom.  The flush
+// converts to FP64.  The FP64 form accumulates with ds_add_f64.
+#include "tiles.h"
 
 namespace pppm {
 
 namespace {
 
 struct SpreadArgs {
-    TileGeo tg;
+    MapGeo g;
     const int* offsets;
     const void* rec;
     double* rho;
     double* rho_user;
-    int pitch_x;  // LDS row pitch (points)
+    const double* stats;  // [1] max |q|
+    int pitch_x;          // LDS row pitch (points)
 };
 
-template <int P, typename R>
+// Largest value of the order-P B-spline (P = 2..7), rounded up.
+__host__ __device__ constexpr double bspline_max(int P)
+{
+    return P == 2 ? 1.0 : P == 3 ? 0.7501 : P == 4 ? 0.6668 : P == 5 ? 0.5991 : P == 6 ? 0.5501 : 0.5111;
+}
+
+// Fixed-point exponent of a tile reading `visits` charges (see above).
+template <int P>
+__device__ __forceinline__ int fixed_point_exponent(int visits, double qmax)
+{
+    const double wm = bspline_max(P);
+    const double bound = (double)visits * qmax * wm * wm * wm;
+    if (!(bound > 0.0)) return 30;
+    int e = (int)floor(log2(1073741824.0 / bound));  // 2^30: one bit of headroom
+    return e < -60 ? -60 : (e > 100 ? 100 : e);
+}
+
+template <typename A> struct Acc;
+template <> struct Acc<int> {
+    // round half up, floor(v + 1/2), in one instruction (v_cvt_rpi_i32_f32)
+    __device__ static void add(int* p, float v)
+    {
+        int r;
+        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+        atomicAdd(p, r);
+    }
+};
+template <> struct Acc<double> {
+    __device__ static void add(double* p, double v) { atomicAdd(p, v); }
+};
+
+template <int P, typename R, typename A>
 __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int lists[3 * MAXL];
-    __shared__ int cnts[3];
-    __shared__ int scratch[17];
-    const TileGeo& tg = a.tg;
+    __shared__ RunTable rt;
+    const MapGeo& g = a.g;
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int tix = tile % tg.ntile[0];
-    const int tiy = (tile / tg.ntile[0]) % tg.ntile[1];
-    const int tiz = tile / (tg.ntile[0] * tg.ntile[1]);
-    const int T0[3] = {tix * tg.B[0], tiy * tg.B[1], tiz * tg.B[2]};
-    const int ext[3] = {min(tg.B[0], tg.K[0] - T0[0]), min(tg.B[1], tg.K[1] - T0[1]),
-                        min(tg.B[2], tg.K[2] - T0[2])};
+    int t[3];
+    tile_coords(g, tile, t);
+    const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
+    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
 
-    // LDS layout: accumulator tile, then the run table
-    R* acc = (R*)smem_raw;
-    const int plane = a.pitch_x * tg.B[1];
-    const int nacc = plane * tg.B[2];
-    int* run_start = (int*)(acc + nacc);
-    int* run_sb = run_start + MAX_RUNS;
-    int* prefix = run_sb + MAX_RUNS;
-
-    for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc[i] = R(0);
-    const int nruns = build_runs(tg, T0, ext, P - 1, a.offsets, lists, cnts, run_start, prefix, run_sb, scratch);
-    if (nruns < 0) return;
-    const int total = prefix[nruns];
+    A* acc = (A*)smem_raw;
+    const int plane = a.pitch_x * g.B[1];
+    const int nacc = plane * g.B[2];
+    for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc[i] = A(0);
+    build_run_table(g, t, a.offsets, rt);
+    __syncthreads();
+    const int total = rt.pre[NRUNS];
+    int e = 0;
+    if (sizeof(A) == 4) e = fixed_point_exponent<P>(total, a.stats[1]);
+    const float scale = ldexpf(1.0f, e);
 
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
-        const int r = find_run(prefix, nruns, v);
-        const RT pr = rec[run_start[r] + (v - prefix[r])];
-        const int sbp = run_sb[r];
-        const int sbc[3] = {sbp & 1023, (sbp >> 10) & 1023, sbp >> 20};
+        const int r = find_run(rt, v);
+        const RT pr = rec[rt.start[r] + (v - rt.pre[r])];
+        const int shp = rt.shift[r], exp_ = rt.ext[r];
         const R tt[3] = {pr.x, pr.y, pr.z};
         int l[3][P];
         unsigned valid[3];
@@ -71,38 +108,45 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
         for (int d = 0; d < 3; ++d) {
             int s;
             R f;
-            decode_axis<R>(tt[d], sbc[d], tg.K[d], s, f);
+            decode_local<R>(tt[d], (exp_ >> (8 * d)) & 255, s, f);
             bspline<P, R, false>(f, w[d], unused);
-            const int dd = s - T0[d];
-            const int wrap = tg.K[d] - T0[d];
+            // tile coordinate of the stencil start: negative for a charge of
+            // the lower neighbour; points past the mesh end wrap only when
+            // the tile spans the whole axis
+            const int dd = s + ((shp >> (8 * d)) & 255) - 128;
             unsigned m = 0;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 int lj = dd + j;
-                if (lj >= wrap) lj -= tg.K[d];
+                if (g.ntile[d] == 1 && lj >= g.K[d]) lj -= g.K[d];
                 l[d][j] = lj;
                 m |= ((unsigned)lj < (unsigned)ext[d]) ? (1u << j) : 0u;
             }
             valid[d] = m;
         }
+        // charge and fixed-point scale folded into the z and x coefficients
         const R qv = pr.w;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            w[2][j] *= qv;
+            w[0][j] *= (R)scale;
+        }
         // z planes in a rolled loop; the plane's z data is element 0 of the
         // register arrays, shifted down one per plane
         unsigned vz = valid[2];
 #pragma unroll 1
         for (int jz = 0; jz < P; ++jz) {
             if (vz & 1u) {
-                const R wz = qv * w[2][0];
-                const int bz = l[2][0] * plane;
+                const R wz = w[2][0];
+                A* pl = acc + l[2][0] * plane;
 #pragma unroll
                 for (int jy = 0; jy < P; ++jy) {
                     if (!(valid[1] >> jy & 1u)) continue;
                     const R wzy = wz * w[1][jy];
-                    R* row = acc + bz + l[1][jy] * a.pitch_x;
+                    A* row = pl + l[1][jy] * a.pitch_x;
 #pragma unroll
-                    for (int jx = 0; jx < P; ++jx) {
-                        if (valid[0] >> jx & 1u) atomicAdd(row + l[0][jx], wzy * w[0][jx]);
-                    }
+                    for (int jx = 0; jx < P; ++jx)
+                        if (valid[0] >> jx & 1u) Acc<A>::add(row + l[0][jx], wzy * w[0][jx]);
                 }
             }
             vz >>= 1;
@@ -120,23 +164,23 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     const int npts = ex * ey * ez;
     for (int i = threadIdx.x; i < npts; i += blockDim.x) {
         const int lx = i % ex, ly = (i / ex) % ey, lz = i / (ex * ey);
-        const double v = (double)acc[lz * plane + ly * a.pitch_x + lx];
-        const size_t gidx = ((size_t)(T0[2] + lz) * tg.K[1] + (T0[1] + ly)) * tg.K[0] + (T0[0] + lx);
+        const double v = ldexp((double)acc[lz * plane + ly * a.pitch_x + lx], -e);
+        const size_t gidx = ((size_t)(T0[2] + lz) * g.K[1] + (T0[1] + ly)) * g.K[0] + (T0[0] + lx);
         a.rho[gidx] = v;
         if (a.rho_user) a.rho_user[gidx] = v;
     }
 }
 
-template <typename R>
+template <typename R, typename A>
 hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
 {
     switch (P) {
-    case 2: k_spread<2, R><<<grid, block, lds, st>>>(a); break;
-    case 3: k_spread<3, R><<<grid, block, lds, st>>>(a); break;
-    case 4: k_spread<4, R><<<grid, block, lds, st>>>(a); break;
-    case 5: k_spread<5, R><<<grid, block, lds, st>>>(a); break;
-    case 6: k_spread<6, R><<<grid, block, lds, st>>>(a); break;
-    case 7: k_spread<7, R><<<grid, block, lds, st>>>(a); break;
+    case 2: k_spread<2, R, A><<<grid, block, lds, st>>>(a); break;
+    case 3: k_spread<3, R, A><<<grid, block, lds, st>>>(a); break;
+    case 4: k_spread<4, R, A><<<grid, block, lds, st>>>(a); break;
+    case 5: k_spread<5, R, A><<<grid, block, lds, st>>>(a); break;
+    case 6: k_spread<6, R, A><<<grid, block, lds, st>>>(a); break;
+    case 7: k_spread<7, R, A><<<grid, block, lds, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -144,59 +188,25 @@ hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t
 
 }  // namespace
 
-TileGeo make_tiles(const pppm_plan_s* pl, const LaunchCfg& c)
+size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes)
 {
-    TileGeo t{};
-    for (int d = 0; d < 3; ++d) {
-        t.K[d] = pl->geo.K[d];
-        t.nsb[d] = pl->geo.nsb[d];
-        t.B[d] = c.tile[d];
-        t.ntile[d] = (t.K[d] + t.B[d] - 1) / t.B[d];
-    }
-    t.ntiles = t.ntile[0] * t.ntile[1] * t.ntile[2];
-    return t;
-}
-
-static int spread_pitch(const LaunchCfg& c) { return c.tile[0] + 1; }
-
-size_t spread_lds_bytes(const pppm_plan_s* pl, const LaunchCfg& c)
-{
-    const size_t nacc = (size_t)spread_pitch(c) * c.tile[1] * c.tile[2];
-    return nacc * pl->rsize + 3 * MAX_RUNS * sizeof(int) + sizeof(int);
-}
-
-int runs_needed(const pppm_plan_s* pl, const LaunchCfg& c, bool spread)
-{
-    // worst case over tiles: own sub-bricks plus the halo ones, per axis
-    long total = 1;
-    const int halo = spread ? pl->p.order - 1 : 0;
-    for (int d = 0; d < 3; ++d) {
-        const int K = pl->geo.K[d];
-        int n;
-        if (c.tile[d] + halo >= K)
-            n = pl->geo.nsb[d];
-        else
-            n = (c.tile[d] + halo + SB - 1) / SB + 1;
-        if (n > MAXL) return 1 << 30;
-        total *= n;
-    }
-    return (int)total;
+    return (size_t)(g.B[0] + 1) * g.B[1] * g.B[2] * acc_bytes;
 }
 
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
 {
-    const LaunchCfg& c = pl->spread_cfg;
     SpreadArgs a{};
-    a.tg = make_tiles(pl, c);
+    a.g = pl->geo;
     a.offsets = pl->offsets;
     a.rec = pl->records;
     a.rho = pl->rho;
     a.rho_user = rho_user;
-    a.pitch_x = spread_pitch(c);
-    const size_t lds = spread_lds_bytes(pl, c);
-    dim3 grid(a.tg.ntiles), block(c.threads);
-    if (pl->mixed) return dispatch_spread<float>(pl->p.order, grid, block, lds, pl->stream, a);
-    return dispatch_spread<double>(pl->p.order, grid, block, lds, pl->stream, a);
+    a.pitch_x = pl->geo.B[0] + 1;
+    a.stats = pl->eterms + 6;
+    const size_t lds = spread_lds_bytes(pl->geo, pl->rsize);
+    dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
+    if (pl->mixed) return dispatch_spread<float, int>(pl->p.order, grid, block, lds, pl->stream, a);
+    return dispatch_spread<double, double>(pl->p.order, grid, block, lds, pl->stream, a);
 }
 
 }  // namespace pppm
