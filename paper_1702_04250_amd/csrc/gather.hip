@@ -38,7 +38,12 @@ struct GatherArgs {
     const double* eterms;
     double self_coef;    // 2 C g / sqrt(pi)
     double bg_coef;      // C pi / (V g^2)
+    int vec_stage;       // tile origins and K_x allow 16-byte staging loads
 };
+
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; };
+template <> struct Vec16<double> { using T = double2; };
 
 template <int P, int MODE, typename R, typename TO>
 __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
@@ -58,25 +63,96 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     R* fld = (R*)smem_raw;
     const int plane = a.pitch_x * a.rows_y;
     const int nsl = plane * (g.B[2] + P - 1);  // one staged mesh
+    const R* __restrict__ fg = (const R*)a.field;
+
+    // The thread's first charge is loaded before the field is staged, and its
+    // stencil evaluated while the staging loads are in flight.
+    using RT = typename Rec<R>::T;
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    int p = first + threadIdx.x;
+    RT pr{};
+    int iu = 0;
+    if (p < last) {
+        pr = rec[p];
+        iu = a.perm[p];
+    }
 
     // stage tile + upper halo of every field mesh (periodic wrap)
-    {
+    if (a.vec_stage) {
+        // 16-byte loads: rows start at multiples of 4 points and K_x % 4 == 0,
+        // so a 4-point chunk never straddles the periodic wrap
+        constexpr int VW = 16 / (int)sizeof(R);  // points per 16-byte chunk
+        using V = typename Vec16<R>::T;
+        const int sx = ext[0] + P - 1, sy = ext[1] + P - 1, sz = ext[2] + P - 1;
+        const int nch = (sx + VW - 1) / VW;  // chunks per row
+        const int n = nch * sy * sz;
+        constexpr int U = 2;
+        for (int i0 = 0; i0 < n; i0 += U * blockDim.x) {
+            V v[U][NC];
+            int li[U], nv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * blockDim.x + threadIdx.x;
+                li[u] = -1;
+                nv[u] = 0;
+                if (i < n) {
+                    const int cx = i % nch, ly = (i / nch) % sy, lz = i / (nch * sy);
+                    const int lx = cx * VW;
+                    int gx = T0[0] + lx, gy = T0[1] + ly, gz = T0[2] + lz;
+                    if (gx >= g.K[0]) gx -= g.K[0];
+                    if (gy >= g.K[1]) gy -= g.K[1];
+                    if (gz >= g.K[2]) gz -= g.K[2];
+                    const size_t gi = ((size_t)gz * g.K[1] + gy) * g.K[0] + gx;
+                    li[u] = lz * plane + ly * a.pitch_x + lx;
+                    nv[u] = min(VW, sx - lx);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[u][c] = *(const V*)(fg + c * a.ncell + gi);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (li[u] >= 0) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const R* e = (const R*)&v[u][c];
+#pragma unroll
+                        for (int k = 0; k < VW; ++k)
+                            if (k < nv[u]) fld[c * nsl + li[u] + k] = e[k];
+                    }
+                }
+        }
+    } else {
+        // 4-byte / 8-byte loads, four in flight per thread before their stores
         const int sx = ext[0] + P - 1, sy = ext[1] + P - 1, sz = ext[2] + P - 1;
         const int n = sx * sy * sz;
-        const R* __restrict__ fg = (const R*)a.field;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const int lx = i % sx, ly = (i / sx) % sy, lz = i / (sx * sy);
-            int gx = T0[0] + lx, gy = T0[1] + ly, gz = T0[2] + lz;
-            if (gx >= g.K[0]) gx -= g.K[0];
-            if (gy >= g.K[1]) gy -= g.K[1];
-            if (gz >= g.K[2]) gz -= g.K[2];
-            const size_t gi = ((size_t)gz * g.K[1] + gy) * g.K[0] + gx;
-            const int li = lz * plane + ly * a.pitch_x + lx;
+        constexpr int U = 4;
+        for (int i0 = 0; i0 < n; i0 += U * blockDim.x) {
+            R v[U][NC];
+            int li[U];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) fld[c * nsl + li] = fg[c * a.ncell + gi];
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * blockDim.x + threadIdx.x;
+                li[u] = -1;
+                if (i < n) {
+                    const int lx = i % sx, ly = (i / sx) % sy, lz = i / (sx * sy);
+                    int gx = T0[0] + lx, gy = T0[1] + ly, gz = T0[2] + lz;
+                    if (gx >= g.K[0]) gx -= g.K[0];
+                    if (gy >= g.K[1]) gy -= g.K[1];
+                    if (gz >= g.K[2]) gz -= g.K[2];
+                    const size_t gi = ((size_t)gz * g.K[1] + gy) * g.K[0] + gx;
+                    li[u] = lz * plane + ly * a.pitch_x + lx;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[u][c] = fg[c * a.ncell + gi];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (li[u] >= 0) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) fld[c * nsl + li[u]] = v[u][c];
+                }
         }
     }
-    __syncthreads();
 
     double gE = 1.0, Q = 0.0;
     if (MODE == GATHER_ADJOINT) {
@@ -84,19 +160,21 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
         Q = a.eterms[4];
     }
 
-    using RT = typename Rec<R>::T;
-    const RT* __restrict__ rec = (const RT*)a.rec;
-    for (int p = first + threadIdx.x; p < last; p += blockDim.x) {
-        const RT pr = rec[p];
+    int l[3] = {0, 0, 0};
+    R w[3][P], dw[3][P];
+    auto prep = [&]() {
         const R tt[3] = {pr.x, pr.y, pr.z};
-        int l[3];
-        R w[3][P], dw[3][P];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             R f;
             decode_local<R>(tt[d], ext[d], l[d], f);  // own charge: start in [0, ext)
             bspline<P, R, DERIV>(f, w[d], dw[d]);
         }
+    };
+    if (p < last) prep();
+    __syncthreads();
+
+    while (p < last) {
         const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
         R o0 = R(0), o1 = R(0), o2 = R(0), o3 = R(0);
         // z planes in a rolled loop: the plane's z coefficients are always
@@ -150,7 +228,6 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                 if (DERIV) dw[2][j] = dw[2][j + 1];
             }
         }
-        const int iu = a.perm[p];
         TO* out = (TO*)a.out0;
         const R qv = pr.w;
         if (MODE == GATHER_IK) {
@@ -170,6 +247,12 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
             }
             if (a.out1)
                 ((TO*)a.out1)[iu] = (TO)(gE * ((double)o3 - a.self_coef * qd - a.bg_coef * Q));
+        }
+        p += blockDim.x;
+        if (p < last) {
+            pr = rec[p];
+            iu = a.perm[p];
+            prep();
         }
     }
 }
@@ -229,6 +312,10 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
     a.bg_coef = pl->p.coulomb_c * M_PI / (V * pl->p.g_ewald * pl->p.g_ewald);
     const size_t rs = pl->rsize;
+    // 16-byte staging needs every row start (a multiple of B_x, or 0 after
+    // the wrap) and K_x to be multiples of the chunk width
+    const int vw = 16 / (int)rs;
+    a.vec_stage = (pl->geo.K[0] % vw == 0) && (pl->geo.B[0] % vw == 0);
     dim3 grid(pl->geo.ntiles), block(c.threads);
     switch (mode) {
     case GATHER_IK:

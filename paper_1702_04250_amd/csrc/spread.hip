@@ -83,6 +83,15 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
     const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
 
+    // The own charges come first in the visit order: the thread's first one
+    // is loaded before the accumulator is cleared and the run table built.
+    using RT = typename Rec<R>::T;
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    const int own0 = a.offsets[tile * NCLASS], own1 = a.offsets[tile * NCLASS + NCLASS];
+    RT pre_rec{};
+    const bool prefetched = own0 + (int)threadIdx.x < own1;
+    if (prefetched) pre_rec = rec[own0 + threadIdx.x];
+
     A* acc = (A*)smem_raw;
     const int plane = a.pitch_x * g.B[1];
     const int nacc = plane * g.B[2];
@@ -94,11 +103,9 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     if (sizeof(A) == 4) e = fixed_point_exponent<P>(total, a.stats[1]);
     const float scale = ldexpf(1.0f, e);
 
-    using RT = typename Rec<R>::T;
-    const RT* __restrict__ rec = (const RT*)a.rec;
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
         const int r = find_run(rt, v);
-        const RT pr = rec[rt.start[r] + (v - rt.pre[r])];
+        const RT pr = (prefetched && v == (int)threadIdx.x) ? pre_rec : rec[rt.start[r] + (v - rt.pre[r])];
         const int shp = rt.shift[r], exp_ = rt.ext[r];
         const R tt[3] = {pr.x, pr.y, pr.z};
         int l[3][P];
