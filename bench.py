@@ -31,6 +31,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PROFILE = os.path.join(ROOT, "profiles", "k_spread_c3_p5_mixed_ad.md")
+# kernel symbol of each timed step (one launch per call)
+STEP_KERNEL = {"make_rho": "k_spread", "fieldforce_ad": "k_gather"}
 METRIC = "particles/s for make_rho+fieldforce (ik & ad) at P=5; % HBM peak; FP32 vs FP64 error"
 
 
@@ -44,7 +47,103 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the headline loop")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output under DIR "
+                         "(subfolders trace, fetch, write, calib_fetch, calib_write) and exit")
     return ap.parse_args()
+
+
+def source_hash():
+    """Hash of the HIP sources: counters taken on other sources are stale."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1702_04250_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+
+    rows = []
+    for path in sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _short(name):
+    name = name.split("(")[0]
+    for key in ("k_spread", "k_gather", "k_map_count", "k_scatter", "k_scan_reduce", "k_scan_apply",
+                "k_solve", "k_energy_final", "k_influence"):
+        if key in name:
+            return key
+    return name[:60]
+
+
+def _counter_per_dispatch(folder, counter, kernel_filter):
+    """Mean of a counter (summed over its instances) per dispatch of the matching kernels."""
+    per = {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter or kernel_filter not in r.get("Kernel_Name", ""):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return (sum(per.values()) / len(per), len(per)) if per else (None, 0)
+
+
+def summarize(folder):
+    """Markdown summary of one profiling session of the benchmark (kernel
+    trace statistics, then FETCH_SIZE / WRITE_SIZE per dispatch scaled by a
+    plain-copy calibration)."""
+    out = [f"source hash: {source_hash()}", ""]
+    stats = _csv_rows(os.path.join(folder, "trace"), "kernel_stats.csv")
+    out.append("| kernel | calls | avg us | min us | max us | total % |")
+    out.append("|---|---|---|---|---|---|")
+    for r in stats:
+        out.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    out.append("")
+    # calibration: KiB the counters report for a copy of known size
+    cal = {}
+    for c, sub in (("FETCH_SIZE", "calib_fetch"), ("WRITE_SIZE", "calib_write")):
+        kib, n = _counter_per_dispatch(os.path.join(folder, sub), c, "copyBuffer")
+        if kib is None:
+            kib, n = _counter_per_dispatch(os.path.join(folder, sub), c, "elementwise_kernel")
+        cal[c] = (1 << 30) / (kib * 1024.0) if kib else None
+        out.append(f"calibration {c}: 1 GiB copy reads as {kib} KiB per dispatch ({n} dispatches) "
+                   f"-> factor {cal[c]}")
+    out.append("")
+    out.append("| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/launch (calibrated) |")
+    out.append("|---|---|---|---|")
+    for k in ("k_spread", "k_gather", "k_map_count", "k_scatter"):
+        f, _ = _counter_per_dispatch(os.path.join(folder, "fetch"), "FETCH_SIZE", k)
+        w, _ = _counter_per_dispatch(os.path.join(folder, "write"), "WRITE_SIZE", k)
+        if f is None or w is None or not cal["FETCH_SIZE"] or not cal["WRITE_SIZE"]:
+            continue
+        tot = f * 1024.0 * cal["FETCH_SIZE"] + w * 1024.0 * cal["WRITE_SIZE"]
+        out.append(f"| {k} | {f:.1f} | {w:.1f} | traffic[{k}] = {tot:.0f} |")
+    return "\n".join(out)
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or was taken on other sources."""
+    import re
+
+    if not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m = re.search(r"source hash: (\w+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(r"traffic\[" + kernel + r"\] = (\d+)", text)
+    return float(m.group(1)) if m else None
 
 
 def algorithmic_bytes(kind, n, cells, prec):
@@ -161,6 +260,9 @@ def cpu_baseline(w, order, pos_r, q_r, budget_s=12.0):
 
 def main():
     args = parse()
+    if args.summarize:
+        print(summarize(args.summarize))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -219,8 +321,8 @@ def main():
         "config": {"workload": f"{w.name}-P{order}: {w.notes}", "n": n, "mesh": list(w.mesh), "order": order,
                    "diff": "ad", "prec": "mixed (f32 stencils/LDS/gathers, f64 mesh charge, FFT-forward and energy)",
                    "io_dtype": "f32", "step": "particle_map + make_rho + poisson + fieldforce"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(STEP_KERNEL[dom]),
                      "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom},
         "kernels_us": {k[:-3]: v for k, v in head.items() if k.endswith("_us") and k != "wall_ms_per_step"},
         "make_rho_fieldforce": {

@@ -52,46 +52,75 @@ __device__ __forceinline__ bool map_coord(double x, double lo, double h, int K, 
     return ok;
 }
 
-// Cardinal B-spline stencil of one axis.  a[k] after building order n holds
-// M_n(f + k); the two-term recursion M_n(x) = [x M_{n-1}(x) + (n - x)
-// M_{n-1}(x - 1)] / (n - 1) is evaluated for the P offsets at once.
-// w[j] = M_P(f + P - 1 - j) is the weight of stencil point s + j and
-// dw[j] = M_{P-1}(f + P - 1 - j) - M_{P-1}(f + P - 2 - j) its d/du.
+// Stencil weights of one axis as polynomials.  On a stencil the weight of
+// point s + j is w_j(f) = M_P(f + P - 1 - j), M_P the cardinal B-spline of
+// order P, a polynomial of degree P - 1 in the fraction f.  Its coefficients
+// in g = f - 1/2 (exact rationals, from the two-term B-spline recursion
+// applied to the polynomial pieces) are c[j][m], w_j = sum_m c[j][m] g^m.
+// Centring on g keeps every power below 1/2 in size, so Horner's rule loses
+// no accuracy near either end of the cell.  Mirror symmetry,
+// w_{P-1-j}(g) = w_j(-g), leaves only the rows j <= (P - 1) / 2.
+template <int P> struct WeightPoly;
+template <> struct WeightPoly<2> {
+    static constexpr double c[1][2] = {{1.0 / 2, -1.0}};
+};
+template <> struct WeightPoly<3> {
+    static constexpr double c[2][3] = {{1.0 / 8, -1.0 / 2, 1.0 / 2}, {3.0 / 4, 0.0, -1.0}};
+};
+template <> struct WeightPoly<4> {
+    static constexpr double c[2][4] = {{1.0 / 48, -1.0 / 8, 1.0 / 4, -1.0 / 6},
+                                       {23.0 / 48, -5.0 / 8, -1.0 / 4, 1.0 / 2}};
+};
+template <> struct WeightPoly<5> {
+    static constexpr double c[3][5] = {{1.0 / 384, -1.0 / 48, 1.0 / 16, -1.0 / 12, 1.0 / 24},
+                                       {19.0 / 96, -11.0 / 24, 1.0 / 4, 1.0 / 6, -1.0 / 6},
+                                       {115.0 / 192, 0.0, -5.0 / 8, 0.0, 1.0 / 4}};
+};
+template <> struct WeightPoly<6> {
+    static constexpr double c[3][6] = {
+        {1.0 / 3840, -1.0 / 384, 1.0 / 96, -1.0 / 48, 1.0 / 48, -1.0 / 120},
+        {79.0 / 1280, -25.0 / 128, 7.0 / 32, -1.0 / 16, -1.0 / 16, 1.0 / 24},
+        {841.0 / 1920, -77.0 / 192, -11.0 / 48, 7.0 / 24, 1.0 / 24, -1.0 / 12}};
+};
+template <> struct WeightPoly<7> {
+    static constexpr double c[4][7] = {
+        {1.0 / 46080, -1.0 / 3840, 1.0 / 768, -1.0 / 288, 1.0 / 192, -1.0 / 240, 1.0 / 720},
+        {361.0 / 23040, -59.0 / 960, 37.0 / 384, -5.0 / 72, 1.0 / 96, 1.0 / 60, -1.0 / 120},
+        {10543.0 / 46080, -289.0 / 768, 79.0 / 768, 43.0 / 288, -17.0 / 192, -1.0 / 48, 1.0 / 48},
+        {5887.0 / 11520, 0.0, -77.0 / 192, 0.0, 7.0 / 48, 0.0, -1.0 / 36}};
+};
+
+// w[j] = w_j(f) and, with DERIV, dw[j] = d w_j / df = M_{P-1}(f + P - 1 - j)
+// - M_{P-1}(f + P - 2 - j) (the derivative along the axis in mesh units).
+// Each mirror pair is evaluated from its even and odd parts in g:
+// w_j = E + g O, w_{P-1-j} = E - g O; dw_j = D + g Q, dw_{P-1-j} = g Q - D.
 template <int P, typename R, bool DERIV>
 __device__ __forceinline__ void bspline(R f, R (&w)[P], R (&dw)[P])
 {
-    R a[P];
-    a[0] = R(1);
+    using C = WeightPoly<P>;
+    const R g = f - R(0.5), g2 = g * g;
 #pragma unroll
-    for (int k = 1; k < P; ++k) a[k] = R(0);
+    for (int j = 0; j < (P + 1) / 2; ++j) {
+        R e = R(0), o = R(0);
 #pragma unroll
-    for (int m = 2; m <= P; ++m) {
-        if (DERIV && m == P) {
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int k1 = P - 1 - j, k2 = P - 2 - j;
-                const R hi = (k1 <= P - 2) ? a[k1] : R(0);
-                const R lo = (k2 >= 0) ? a[k2] : R(0);
-                dw[j] = hi - lo;
-            }
+        for (int m = P - 1; m >= 0; --m) {
+            if (m % 2 == 0) e = e * g2 + R(C::c[j][m]);
+            else o = o * g2 + R(C::c[j][m]);
         }
-        const R inv = R(1) / R(m - 1);
-        R next[P];
+        w[j] = e + g * o;
+        if (P - 1 - j != j) w[P - 1 - j] = e - g * o;
+        if (DERIV) {
+            // derivative coefficients (m + 1) c[j][m + 1], m = 0 .. P - 2
+            R de = R(0), dq = R(0);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (k < m) {
-                const R left = (k < m - 1) ? a[k] : R(0);
-                const R right = (k >= 1) ? a[k - 1] : R(0);
-                next[k] = ((f + R(k)) * left + (R(m) - f - R(k)) * right) * inv;
-            } else {
-                next[k] = R(0);
+            for (int m = P - 2; m >= 0; --m) {
+                if (m % 2 == 0) de = de * g2 + R((m + 1) * C::c[j][m + 1]);
+                else dq = dq * g2 + R((m + 1) * C::c[j][m + 1]);
             }
+            dw[j] = de + g * dq;
+            if (P - 1 - j != j) dw[P - 1 - j] = g * dq - de;
         }
-#pragma unroll
-        for (int k = 0; k < P; ++k) a[k] = next[k];
     }
-#pragma unroll
-    for (int j = 0; j < P; ++j) w[j] = a[P - 1 - j];
 }
 
 // Inclusive warp-level scan over a 64-wide wavefront.

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(MAP_THREADS) void k_map_count(int n, const TI* __re
         if (!isfinite(qi)) ok = false;
         if (!ok && g.check_finite) atomicOr(flags, 1);
         int sl[3];
-        slot[i] = atomicAdd(&count[bin_of(g, s, sl)], 1);
+        slot[i] = atomicAdd(&count[bin_of(g, s, sl) * NSUB + (i & (NSUB - 1))], 1);
     }
     // charge sums for the self and background energy terms, and max |q|
     // (which bounds the mesh charge for the fixed-point spread)
@@ -108,8 +108,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(int nbins_, int nb
 
 // Exclusive prefix of the counts -> offsets; counts are reset to zero for the
 // next call.  offsets[nbins] = number of particles.  Block 0 also writes
-// stats[0] = largest bin count and stats[1] = max |q| (from the particle-map
-// partials), which bound the mesh charge of any point.
+// stats[0] = largest (sub-)bin count and stats[1] = max |q| (from the
+// particle-map partials); max |q| bounds the mesh charge of any point.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nblocks, int* __restrict__ count,
                                                               const int* __restrict__ part,
                                                               int* __restrict__ offsets, int nqblocks,
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
     for (int d = 0; d < 3; ++d)
         map_coord((double)pos[3 * (size_t)i + d], g.lo[d], g.h[d], g.K[d], g.shift, s[d], f[d]);
     int sl[3];
-    const int dest = offsets[bin_of(g, s, sl)] + slot[i];
+    const int dest = offsets[bin_of(g, s, sl) * NSUB + (i & (NSUB - 1))] + slot[i];
     typename Rec<R>::T r;
     r.x = (R)((double)sl[0] + f[0]);
     r.y = (R)((double)sl[1] + f[1]);
@@ -218,9 +218,10 @@ hipError_t launch_map_count(pppm_plan_s* pl, int64_t n, const void* pos, const v
 
 hipError_t launch_scan(pppm_plan_s* pl)
 {
-    const int nb = grid_for(pl->nbins, SCAN_BLOCK);
-    k_scan_reduce<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)pl->nbins, nb, pl->count, pl->scan_part);
-    k_scan_apply<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)pl->nbins, nb, pl->count, pl->scan_part, pl->offsets,
+    const int64_t nsub = pl->nbins * NSUB;
+    const int nb = grid_for(nsub, SCAN_BLOCK);
+    k_scan_reduce<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)nsub, nb, pl->count, pl->scan_part);
+    k_scan_apply<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)nsub, nb, pl->count, pl->scan_part, pl->offsets,
                                                       (int)pl->qpart_blocks, pl->qpart, pl->eterms + 6);
     return hipGetLastError();
 }

@@ -138,6 +138,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize);
     const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize);
     const size_t lim = pl->lds_limit - LDS_STATIC < lds_budget ? pl->lds_limit - LDS_STATIC : lds_budget;
+    if ((int64_t)g.ntiles * NCLASS > pl->max_bins) return "tile too fine for the plan's bin arrays";
     if (lds_s > lim || lds_g > lim || lds_a > lim)
         return "tile needs " + std::to_string(lds_s > lds_g ? lds_s : lds_g) + " bytes of LDS";
     pl->geo = g;
@@ -159,16 +160,23 @@ int split_edge(int K, int b, int P)
     return K;  // a single tile
 }
 
-// Default tile: the first usable shape of a preference list (16 x 16 x 8 was
-// fastest on the 128^3 mesh of the benchmark), each axis split evenly.
+// Default tile: the first usable shape of a preference list, each axis split
+// evenly.  On the 128^3 mesh of the benchmark (P = 5, mixed precision) a
+// 32 x 16 x 8 tile gave the lowest make_rho + ad gather time and 32 x 8 x 8
+// the lowest make_rho + ik gather time (the ik gather stages three meshes).
 std::string default_tile(pppm_plan_s* pl)
 {
-    static const int prefs[][3] = {{16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
+    static const int prefs_ad[][3] = {{32, 16, 8}, {32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
+    static const int prefs_ik[][3] = {{32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
+    const bool ik = pl->p.diff == PPPM_DIFF_IK;
+    const int (*prefs)[3] = ik ? prefs_ik : prefs_ad;
+    const int nprefs = ik ? 6 : 7;
     std::string why;
     // first within the LDS size that keeps several workgroups per CU, then
     // anything the device holds (small meshes that cannot be split)
     for (size_t budget : {LDS_PREFERRED, pl->lds_limit}) {
-        for (const auto& pref : prefs) {
+        for (int k = 0; k < nprefs; ++k) {
+            const int* pref = prefs[k];
             int B[3];
             for (int d = 0; d < 3; ++d) B[d] = split_edge(pl->geo.K[d], pref[d], pl->p.order);
             if (B[0] > 64 || B[1] > 64 || B[2] > 64) {
@@ -360,14 +368,16 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
     // bins sized for the finest allowed tiling (edges of 4 points)
     const int64_t max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
+    pl->max_bins = max_bins;
+    const int64_t max_sub = max_bins * NSUB;
 
     const int64_t nmax = params->max_particles;
     const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
     const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
     const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
-    const int64_t scan_blocks = (max_bins + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    if ((st = dmalloc(pl, &pl->count, max_bins * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->offsets, (max_bins + 1) * sizeof(int))) != PPPM_OK ||
+    const int64_t scan_blocks = (max_sub + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if ((st = dmalloc(pl, &pl->count, max_sub * sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->offsets, (max_sub + 1) * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->scan_part, 2 * scan_blocks * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
@@ -383,7 +393,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
 
-    e = hipMemsetAsync(pl->count, 0, max_bins * sizeof(int), pl->stream);
+    e = hipMemsetAsync(pl->count, 0, max_sub * sizeof(int), pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 8 * sizeof(double), pl->stream);
     if (e != hipSuccess) {

@@ -18,6 +18,11 @@ namespace pppm {
 // upper face along d, i.e. when the stencil reaches into the next tile along
 // d.  Each tile thus owns 8 consecutive bins.
 constexpr int NCLASS = 8;
+// Each bin is counted in NSUB sub-bins (picked by the particle index), so
+// that the device-scope atomic counters of the particle map see NSUB times
+// less contention.  The sub-bins of a bin are adjacent in the binned order:
+// bin b starts at offsets[b * NSUB].
+constexpr int NSUB = 16;
 constexpr int MAP_THREADS = 256;
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 4;  // counts per thread per scan block
@@ -55,15 +60,16 @@ struct pppm_plan_s {
     int64_t ncell = 0;   // Kx Ky Kz
     int64_t nspec = 0;   // Kz Ky (Kx/2 + 1): half spectrum of a real transform
     int64_t nbins = 0;   // tiles x NCLASS
+    int64_t max_bins = 0;  // bins the count / offset arrays hold (each NSUB sub-bins)
     int ncomp = 1;       // field meshes of the forward gather: 3 (ik) or 1 (ad)
     bool mixed = true;
     size_t rsize = 4;    // bytes of the particle-side real type (float / double)
 
     // device buffers owned by the plan
-    int* count = nullptr;      // [nbins] charges per bin (kept zero between calls)
-    int* offsets = nullptr;    // [nbins + 1] exclusive prefix of count
-    int* scan_part = nullptr;  // [2 * ceil(nbins / SCAN_BLOCK)] chunk sums, then chunk maxima of count
-    int* slot = nullptr;       // [max_particles] rank of a particle within its bin
+    int* count = nullptr;      // [nbins * NSUB] charges per sub-bin (kept zero between calls)
+    int* offsets = nullptr;    // [nbins * NSUB + 1] exclusive prefix of count
+    int* scan_part = nullptr;  // [2 * ceil(nbins * NSUB / SCAN_BLOCK)] chunk sums, then chunk maxima of count
+    int* slot = nullptr;       // [max_particles] rank of a particle within its sub-bin
     void* records = nullptr;   // [max_particles] float4 / double4 (t_x, t_y, t_z, q) in binned order;
                                // t = stencil start within the tile + fraction
     int* perm = nullptr;       // [max_particles] binned position -> caller index

@@ -36,7 +36,9 @@ struct SpreadArgs {
     double* rho;
     double* rho_user;
     const double* stats;  // [1] max |q|
-    int pitch_x;          // LDS row pitch (points)
+    int pitch_x;          // LDS row pitch (points): B_x + 2 (P - 1)
+    int rows_y;           // LDS rows per plane: B_y, + P - 1 on a single-tile axis
+    int planes_z;         // LDS planes: B_z, + P - 1 on a single-tile axis
 };
 
 // Largest value of the order-P B-spline (P = 2..7), rounded up.
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ RunTable rt;
     const MapGeo& g = a.g;
+    constexpr int H = P - 1;  // halo / margin width
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     int t[3];
@@ -83,33 +86,42 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
     const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
 
-    // The own charges come first in the visit order: the thread's first one
-    // is loaded before the accumulator is cleared and the run table built.
+    // The thread's first visit is an own charge whenever the tile has enough
+    // of them; its record is loaded before the accumulator is cleared.
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
-    const int own0 = a.offsets[tile * NCLASS], own1 = a.offsets[tile * NCLASS + NCLASS];
-    RT pre_rec{};
-    const bool prefetched = own0 + (int)threadIdx.x < own1;
-    if (prefetched) pre_rec = rec[own0 + threadIdx.x];
+    const int own0 = a.offsets[tile * NCLASS * NSUB], own1 = a.offsets[(tile + 1) * NCLASS * NSUB];
+    RT cur{};
+    if (own0 + (int)threadIdx.x < own1) cur = rec[own0 + threadIdx.x];
 
+    // Accumulator layout: rows of pitch_x points hold x in [-H, B_x + H)
+    // (x index + H); rows_y rows per plane, planes_z planes.  The x margins
+    // take the parts of stencils that fall outside the tile along x, so the
+    // x loop needs no test; along y and z out-of-tile points are skipped.  On
+    // an axis that is a single tile, stencils wrap: the points past K land in
+    // margin rows / planes (y, z) or the right x margin and are folded back
+    // onto the start of the axis before the flush.
     A* acc = (A*)smem_raw;
-    const int plane = a.pitch_x * g.B[1];
-    const int nacc = plane * g.B[2];
+    const int pitch = a.pitch_x;
+    const int plane = pitch * a.rows_y;
+    const int nacc = plane * a.planes_z;
     for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc[i] = A(0);
     build_run_table(g, t, a.offsets, rt);
     __syncthreads();
     const int total = rt.pre[NRUNS];
     int e = 0;
     if (sizeof(A) == 4) e = fixed_point_exponent<P>(total, a.stats[1]);
-    const float scale = ldexpf(1.0f, e);
+    const R scale = (R)ldexp(1.0, e);
+    // valid y rows / z planes: [0, lim)
+    const int lim_y = g.ntile[1] == 1 ? g.K[1] + H : ext[1];
+    const int lim_z = g.ntile[2] == 1 ? g.K[2] + H : ext[2];
 
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
         const int r = find_run(rt, v);
-        const RT pr = (prefetched && v == (int)threadIdx.x) ? pre_rec : rec[rt.start[r] + (v - rt.pre[r])];
+        if (v >= own1 - own0 || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
         const int shp = rt.shift[r], exp_ = rt.ext[r];
-        const R tt[3] = {pr.x, pr.y, pr.z};
-        int l[3][P];
-        unsigned valid[3];
+        const R tt[3] = {cur.x, cur.y, cur.z};
+        int dd[3];
         R w[3][P], unused[P];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -118,60 +130,83 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
             decode_local<R>(tt[d], (exp_ >> (8 * d)) & 255, s, f);
             bspline<P, R, false>(f, w[d], unused);
             // tile coordinate of the stencil start: negative for a charge of
-            // the lower neighbour; points past the mesh end wrap only when
-            // the tile spans the whole axis
-            const int dd = s + ((shp >> (8 * d)) & 255) - 128;
-            unsigned m = 0;
+            // the lower neighbour
+            dd[d] = s + ((shp >> (8 * d)) & 255) - 128;
+        }
+        unsigned vy = 0, vz = 0;
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                int lj = dd + j;
-                if (g.ntile[d] == 1 && lj >= g.K[d]) lj -= g.K[d];
-                l[d][j] = lj;
-                m |= ((unsigned)lj < (unsigned)ext[d]) ? (1u << j) : 0u;
-            }
-            valid[d] = m;
+        for (int j = 0; j < P; ++j) {
+            vy |= ((unsigned)(dd[1] + j) < (unsigned)lim_y) ? (1u << j) : 0u;
+            vz |= ((unsigned)(dd[2] + j) < (unsigned)lim_z) ? (1u << j) : 0u;
         }
         // charge and fixed-point scale folded into the z and x coefficients
-        const R qv = pr.w;
+        const R qv = cur.w;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             w[2][j] *= qv;
-            w[0][j] *= (R)scale;
+            w[0][j] *= scale;
         }
-        // z planes in a rolled loop; the plane's z data is element 0 of the
-        // register arrays, shifted down one per plane
-        unsigned vz = valid[2];
+        // first point of the stencil; only valid rows and planes are touched
+        A* pz = acc + dd[2] * plane + dd[1] * pitch + (dd[0] + H);
+        // z planes in a rolled loop; the plane's z weight is element 0 of
+        // the register array, shifted down one per plane
 #pragma unroll 1
         for (int jz = 0; jz < P; ++jz) {
             if (vz & 1u) {
                 const R wz = w[2][0];
-                A* pl = acc + l[2][0] * plane;
 #pragma unroll
                 for (int jy = 0; jy < P; ++jy) {
-                    if (!(valid[1] >> jy & 1u)) continue;
-                    const R wzy = wz * w[1][jy];
-                    A* row = pl + l[1][jy] * a.pitch_x;
+                    if (vy >> jy & 1u) {
+                        const R wzy = wz * w[1][jy];
+                        A* row = pz + jy * pitch;
 #pragma unroll
-                    for (int jx = 0; jx < P; ++jx)
-                        if (valid[0] >> jx & 1u) Acc<A>::add(row + l[0][jx], wzy * w[0][jx]);
+                        for (int jx = 0; jx < P; ++jx) Acc<A>::add(row + jx, wzy * w[0][jx]);
+                    }
                 }
             }
             vz >>= 1;
+            pz += plane;
 #pragma unroll
-            for (int j = 0; j < P - 1; ++j) {
-                w[2][j] = w[2][j + 1];
-                l[2][j] = l[2][j + 1];
-            }
+            for (int j = 0; j < P - 1; ++j) w[2][j] = w[2][j + 1];
         }
     }
     __syncthreads();
+
+    // periodic fold of single-tile axes: points K .. K + H - 1 onto 0 .. H - 1
+    if (g.ntile[0] == 1) {
+        const int rows = a.rows_y * a.planes_z;
+        for (int i = threadIdx.x; i < rows * H; i += blockDim.x) {
+            A* row = acc + (i / H) * pitch + H;
+            const int x = i % H;
+            row[x] += row[g.K[0] + x];
+        }
+        __syncthreads();
+    }
+    if (g.ntile[1] == 1) {
+        const int n = ext[0] * H * a.planes_z;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int x = i % ext[0], y = (i / ext[0]) % H, z = i / (ext[0] * H);
+            A* p = acc + z * plane + H + x;
+            p[y * pitch] += p[(g.K[1] + y) * pitch];
+        }
+        __syncthreads();
+    }
+    if (g.ntile[2] == 1) {
+        const int n = ext[0] * ext[1] * H;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int x = i % ext[0], y = (i / ext[0]) % ext[1], z = i / (ext[0] * ext[1]);
+            A* p = acc + y * pitch + H + x;
+            p[z * plane] += p[(g.K[2] + z) * plane];
+        }
+        __syncthreads();
+    }
 
     // flush: every point of the tile is owned here; coalesced FP64 stores
     const int ex = ext[0], ey = ext[1], ez = ext[2];
     const int npts = ex * ey * ez;
     for (int i = threadIdx.x; i < npts; i += blockDim.x) {
         const int lx = i % ex, ly = (i / ex) % ey, lz = i / (ex * ey);
-        const double v = ldexp((double)acc[lz * plane + ly * a.pitch_x + lx], -e);
+        const double v = ldexp((double)acc[lz * plane + ly * pitch + H + lx], -e);
         const size_t gidx = ((size_t)(T0[2] + lz) * g.K[1] + (T0[1] + ly)) * g.K[0] + (T0[0] + lx);
         a.rho[gidx] = v;
         if (a.rho_user) a.rho_user[gidx] = v;
@@ -195,9 +230,13 @@ hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t
 
 }  // namespace
 
+namespace {
+int spread_rows(const MapGeo& g, int d) { return g.B[d] + (g.ntile[d] == 1 ? g.halo : 0); }
+}  // namespace
+
 size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes)
 {
-    return (size_t)(g.B[0] + 1) * g.B[1] * g.B[2] * acc_bytes;
+    return (size_t)(g.B[0] + 2 * g.halo) * spread_rows(g, 1) * spread_rows(g, 2) * acc_bytes;
 }
 
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
@@ -208,7 +247,9 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
     a.rec = pl->records;
     a.rho = pl->rho;
     a.rho_user = rho_user;
-    a.pitch_x = pl->geo.B[0] + 1;
+    a.pitch_x = pl->geo.B[0] + 2 * pl->geo.halo;
+    a.rows_y = spread_rows(pl->geo, 1);
+    a.planes_z = spread_rows(pl->geo, 2);
     a.stats = pl->eterms + 6;
     const size_t lds = spread_lds_bytes(pl->geo, pl->rsize);
     dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
