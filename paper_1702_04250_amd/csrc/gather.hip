@@ -58,7 +58,7 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     tile_coords(g, tile, t);
     const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
     const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
-    const int first = a.offsets[tile * NCLASS * NSUB], last = a.offsets[(tile + 1) * NCLASS * NSUB];
+    const int first = a.offsets[tile * NCLASS * g.bin_stride], last = a.offsets[(tile + 1) * NCLASS * g.bin_stride];
 
     R* fld = (R*)smem_raw;
     const int plane = a.pitch_x * a.rows_y;

@@ -1,7 +1,15 @@
 // Particle map (the per-atom part of the mapping functions, paper Section
 // 3.1): wrap each charge into the box, find its stencil start and fraction,
-// and counting-sort the charges by (tile, halo class) bin.  Three passes:
-// count (with per-bin rank), scan, scatter into binned order.
+// and counting-sort the charges by (tile, halo class) bin.  Passes: count
+// (with a rank per charge), scan, scatter into binned order.
+//
+// Two forms of the count.  Histogram form (bins fit in LDS): block b bins a
+// chunk of consecutive charges in an LDS histogram, ranking each charge with
+// an LDS atomic; a column pass turns the per-block counts into per-block
+// offsets within each bin.  Device-scope atomics are avoided: on a chip whose
+// XCDs have separate L2 caches they are resolved past the L2 and throttle a
+// counting pass over half a million charges.  Atomic form (otherwise): one
+// device-scope atomic per charge on one of NSUB sub-bins of its bin.
 #include "tiles.h"
 
 namespace pppm {
@@ -24,6 +32,37 @@ __device__ __forceinline__ int bin_of(const MapGeo& g, const int (&s)[3], int (&
     return tile * NCLASS + class_pos(cls);
 }
 
+// Block-wide sums of q and q^2 and max |q| into qpart[3 * blockIdx.x ..].
+template <int THREADS>
+__device__ __forceinline__ void charge_sums(double a, double b, double c, double* __restrict__ qpart)
+{
+    __shared__ double red[3][THREADS / 64];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        a += __shfl_down(a, d, 64);
+        b += __shfl_down(b, d, 64);
+        c = fmax(c, __shfl_down(c, d, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wid] = a;
+        red[1][wid] = b;
+        red[2][wid] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0, sc = 0.0;
+        for (int w = 0; w < THREADS / 64; ++w) {
+            sa += red[0][w];
+            sb += red[1][w];
+            sc = fmax(sc, red[2][w]);
+        }
+        qpart[3 * blockIdx.x] = sa;
+        qpart[3 * blockIdx.x + 1] = sb;
+        qpart[3 * blockIdx.x + 2] = sc;
+    }
+}
+
 template <typename TI>
 __global__ __launch_bounds__(MAP_THREADS) void k_map_count(int n, const TI* __restrict__ pos,
                                                             const TI* __restrict__ q, MapGeo g,
@@ -32,7 +71,6 @@ __global__ __launch_bounds__(MAP_THREADS) void k_map_count(int n, const TI* __re
                                                             double* __restrict__ qpart,
                                                             int* __restrict__ flags)
 {
-    __shared__ double red[3][MAP_THREADS / 64];
     const int i = blockIdx.x * MAP_THREADS + threadIdx.x;
     double qi = 0.0;
     if (i < n) {
@@ -50,30 +88,160 @@ __global__ __launch_bounds__(MAP_THREADS) void k_map_count(int n, const TI* __re
     }
     // charge sums for the self and background energy terms, and max |q|
     // (which bounds the mesh charge for the fixed-point spread)
-    double a = qi, b = qi * qi, c = fabs(qi);
+    charge_sums<MAP_THREADS>(qi, qi * qi, fabs(qi), qpart);
+}
+
+// Histogram count: block b maps charges [b * chunk, (b + 1) * chunk) and
+// counts them per bin in LDS; slot[i] = rank of charge i among the block's
+// charges of its bin; hist[b][bin] = the block's count.
+template <typename TI>
+__global__ __launch_bounds__(HIST_THREADS) void k_hist_count(int n, int chunk, int nbins, const TI* __restrict__ pos,
+                                                              const TI* __restrict__ q, MapGeo g,
+                                                              int* __restrict__ slot, int* __restrict__ hist,
+                                                              double* __restrict__ qpart, int* __restrict__ flags)
+{
+    extern __shared__ int lhist[];
+    for (int b = threadIdx.x; b < nbins; b += HIST_THREADS) lhist[b] = 0;
+    __syncthreads();
+    const int i0 = blockIdx.x * chunk;
+    const int i1 = min(n, i0 + chunk);
+    double a = 0.0, b2 = 0.0, c = 0.0;
+    // up to four charges per thread per pass, their loads issued together
+    constexpr int U = 4;
+    for (int ib = i0 + threadIdx.x; ib < i1; ib += U * HIST_THREADS) {
+        TI x[U][3], qq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = ib + u * HIST_THREADS;
+            if (i < i1) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) x[u][d] = pos[3 * (size_t)i + d];
+                qq[u] = q[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = ib + u * HIST_THREADS;
+            if (i >= i1) break;
+            int s[3];
+            double f[3];
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ok &= map_coord((double)x[u][d], g.lo[d], g.h[d], g.K[d], g.shift, s[d], f[d]);
+            const double qi = (double)qq[u];
+            if (!isfinite(qi)) ok = false;
+            if (!ok && g.check_finite) atomicOr(flags, 1);
+            int sl[3];
+            slot[i] = atomicAdd(&lhist[bin_of(g, s, sl)], 1);
+            a += qi;
+            b2 += qi * qi;
+            c = fmax(c, fabs(qi));
+        }
+    }
+    charge_sums<HIST_THREADS>(a, b2, c, qpart);  // synchronises the block
+    int* __restrict__ row = hist + (size_t)blockIdx.x * nbins;
+    for (int b = threadIdx.x; b < nbins; b += HIST_THREADS) row[b] = lhist[b];
+}
+
+// Column pass.  A workgroup takes PREFIX_BINS bins and splits the histogram
+// blocks into PREFIX_SEGS segments: thread (bin, segment) holds its
+// segment's counts in registers, the segment sums are combined through LDS,
+// and the counts become their exclusive prefix over blocks (the block's
+// offset within the bin); the bin total goes to count[bin].
+constexpr int PREFIX_THREADS = 256;
+constexpr int PREFIX_SEGS = 4;
+constexpr int PREFIX_BINS = PREFIX_THREADS / PREFIX_SEGS;
+constexpr int PREFIX_SEG_MAX = HIST_MAX_BLOCKS / PREFIX_SEGS;
+
+__global__ __launch_bounds__(PREFIX_THREADS) void k_hist_prefix(int nbins, int nblocks, int* __restrict__ hist,
+                                                                 int* __restrict__ count)
+{
+    __shared__ int segsum[PREFIX_SEGS][PREFIX_BINS];
+    const int lb = threadIdx.x % PREFIX_BINS, seg = threadIdx.x / PREFIX_BINS;
+    const int b = blockIdx.x * PREFIX_BINS + lb;
+    const int seglen = (nblocks + PREFIX_SEGS - 1) / PREFIX_SEGS;
+    const int k0 = seg * seglen, k1 = min(nblocks, k0 + seglen);
+    int v[PREFIX_SEG_MAX];
+    int sum = 0;
+#pragma unroll
+    for (int u = 0; u < PREFIX_SEG_MAX; ++u) {
+        v[u] = (b < nbins && k0 + u < k1) ? hist[(size_t)(k0 + u) * nbins + b] : 0;
+        sum += v[u];
+    }
+    segsum[seg][lb] = sum;
+    __syncthreads();
+    int run = 0, bin_total = 0;
+#pragma unroll
+    for (int s2 = 0; s2 < PREFIX_SEGS; ++s2) {
+        const int x = segsum[s2][lb];
+        run += (s2 < seg) ? x : 0;
+        bin_total += x;
+    }
+    if (b < nbins) {
+#pragma unroll
+        for (int u = 0; u < PREFIX_SEG_MAX; ++u)
+            if (k0 + u < k1) {
+                hist[(size_t)(k0 + u) * nbins + b] = run;
+                run += v[u];
+            }
+        if (seg == 0) count[b] = bin_total;
+    }
+}
+
+// Single-workgroup exclusive scan of the bin totals (nbins <= HIST_MAX_BINS)
+// into offsets[0 .. nbins]; zeroes count again; stats[0] = largest bin,
+// stats[1] = max |q| from the count pass's partials.
+constexpr int SSCAN_THREADS = 1024;
+constexpr int SSCAN_PER = HIST_MAX_BINS / SSCAN_THREADS;
+
+__global__ __launch_bounds__(SSCAN_THREADS) void k_scan_single(int nbins, int* __restrict__ count,
+                                                                int* __restrict__ offsets, int nqblocks,
+                                                                const double* __restrict__ qpart,
+                                                                double* __restrict__ stats)
+{
+    __shared__ int scratch[17];
+    __shared__ double smax[2][SSCAN_THREADS / 64];
+    const int per = (nbins + SSCAN_THREADS - 1) / SSCAN_THREADS;  // <= SSCAN_PER
+    const int j0 = threadIdx.x * per;
+    int c[SSCAN_PER];
+    int sum = 0, mc = 0;
+#pragma unroll
+    for (int u = 0; u < SSCAN_PER; ++u) {
+        c[u] = (u < per && j0 + u < nbins) ? count[j0 + u] : 0;
+        sum += c[u];
+        mc = max(mc, c[u]);
+    }
+    int total;
+    int ex = block_exclusive_scan(sum, scratch, &total);
+#pragma unroll
+    for (int u = 0; u < SSCAN_PER; ++u)
+        if (u < per && j0 + u < nbins) {
+            offsets[j0 + u] = ex;
+            ex += c[u];
+            count[j0 + u] = 0;
+        }
+    double mq = 0.0;
+    for (int j = threadIdx.x; j < nqblocks; j += SSCAN_THREADS) mq = fmax(mq, qpart[3 * j + 2]);
+    double mcd = (double)mc;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
-        a += __shfl_down(a, d, 64);
-        b += __shfl_down(b, d, 64);
-        c = fmax(c, __shfl_down(c, d, 64));
+        mcd = fmax(mcd, __shfl_down(mcd, d, 64));
+        mq = fmax(mq, __shfl_down(mq, d, 64));
     }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wid] = a;
-        red[1][wid] = b;
-        red[2][wid] = c;
+    if ((threadIdx.x & 63) == 0) {
+        smax[0][threadIdx.x >> 6] = mcd;
+        smax[1][threadIdx.x >> 6] = mq;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0, sc = 0.0;
-        for (int w = 0; w < MAP_THREADS / 64; ++w) {
-            sa += red[0][w];
-            sb += red[1][w];
-            sc = fmax(sc, red[2][w]);
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < SSCAN_THREADS / 64; ++w) {
+            x = fmax(x, smax[0][w]);
+            y = fmax(y, smax[1][w]);
         }
-        qpart[3 * blockIdx.x] = sa;
-        qpart[3 * blockIdx.x + 1] = sb;
-        qpart[3 * blockIdx.x + 2] = sc;
+        stats[0] = x;
+        stats[1] = y;
+        offsets[nbins] = total;
     }
 }
 
@@ -172,11 +340,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nbl
     if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) offsets[nbins_] = sbase + total;
 }
 
+// Scatter into binned order.  Histogram form (hist != nullptr): destination
+// = bin offset + the block's offset within the bin + rank; atomic form:
+// sub-bin offset + rank.
 template <typename TI, typename R>
 __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __restrict__ pos,
                                                           const TI* __restrict__ q, MapGeo g,
                                                           const int* __restrict__ offsets,
                                                           const int* __restrict__ slot,
+                                                          const int* __restrict__ hist, int chunk, int nbins,
                                                           typename Rec<R>::T* __restrict__ rec,
                                                           int* __restrict__ perm)
 {
@@ -188,7 +360,9 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
     for (int d = 0; d < 3; ++d)
         map_coord((double)pos[3 * (size_t)i + d], g.lo[d], g.h[d], g.K[d], g.shift, s[d], f[d]);
     int sl[3];
-    const int dest = offsets[bin_of(g, s, sl) * NSUB + (i & (NSUB - 1))] + slot[i];
+    const int bin = bin_of(g, s, sl);
+    const int dest = hist ? offsets[bin] + hist[(size_t)(i / chunk) * nbins + bin] + slot[i]
+                          : offsets[bin * NSUB + (i & (NSUB - 1))] + slot[i];
     typename Rec<R>::T r;
     r.x = (R)((double)sl[0] + f[0]);
     r.y = (R)((double)sl[1] + f[1]);
@@ -204,6 +378,30 @@ inline int grid_for(int64_t n, int threads) { return (int)((n + threads - 1) / t
 
 hipError_t launch_map_count(pppm_plan_s* pl, int64_t n, const void* pos, const void* q)
 {
+    if (pl->geo.bin_stride == 1) {
+        // histogram form: about HIST_CHUNK charges per block
+        const int nbins = (int)pl->nbins;
+        int nb = (int)((n + HIST_CHUNK - 1) / HIST_CHUNK);
+        nb = nb < 1 ? 1 : (nb > HIST_MAX_BLOCKS ? HIST_MAX_BLOCKS : nb);
+        const int chunk = (int)((n + nb - 1) / nb);
+        pl->hist_blocks = nb;
+        pl->hist_chunk = chunk > 0 ? chunk : 1;
+        pl->qpart_blocks = nb;
+        const size_t lds = (size_t)nbins * sizeof(int);
+        if (pl->p.io_dtype == PPPM_F32)
+            k_hist_count<float><<<nb, HIST_THREADS, lds, pl->stream>>>(
+                (int)n, pl->hist_chunk, nbins, (const float*)pos, (const float*)q, pl->geo, pl->slot, pl->hist,
+                pl->qpart, pl->flags);
+        else
+            k_hist_count<double><<<nb, HIST_THREADS, lds, pl->stream>>>(
+                (int)n, pl->hist_chunk, nbins, (const double*)pos, (const double*)q, pl->geo, pl->slot, pl->hist,
+                pl->qpart, pl->flags);
+        k_hist_prefix<<<grid_for(nbins, PREFIX_BINS), PREFIX_THREADS, 0, pl->stream>>>(nbins, nb, pl->hist,
+                                                                                          pl->count);
+        k_scan_single<<<1, SSCAN_THREADS, 0, pl->stream>>>(nbins, pl->count, pl->offsets, nb, pl->qpart,
+                                                           pl->eterms + 6);
+        return hipGetLastError();
+    }
     const int blocks = grid_for(n, MAP_THREADS);
     pl->qpart_blocks = blocks;
     if (blocks == 0) return hipGetLastError();
@@ -218,7 +416,8 @@ hipError_t launch_map_count(pppm_plan_s* pl, int64_t n, const void* pos, const v
 
 hipError_t launch_scan(pppm_plan_s* pl)
 {
-    const int64_t nsub = pl->nbins * NSUB;
+    if (pl->geo.bin_stride == 1) return hipGetLastError();  // scanned by the histogram count
+    const int64_t nsub = pl->nbins * pl->geo.bin_stride;
     const int nb = grid_for(nsub, SCAN_BLOCK);
     k_scan_reduce<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)nsub, nb, pl->count, pl->scan_part);
     k_scan_apply<<<nb, SCAN_THREADS, 0, pl->stream>>>((int)nsub, nb, pl->count, pl->scan_part, pl->offsets,
@@ -231,22 +430,25 @@ hipError_t launch_scatter(pppm_plan_s* pl, int64_t n, const void* pos, const voi
     const int blocks = grid_for(n, MAP_THREADS);
     if (blocks == 0) return hipGetLastError();
     const bool f32io = pl->p.io_dtype == PPPM_F32;
+    const bool h = pl->geo.bin_stride == 1;
+    const int* hist = h ? pl->hist : nullptr;
+    const int chunk = h ? pl->hist_chunk : 1, nbins = (int)pl->nbins;
     if (pl->mixed) {
         auto* rec = (float4*)pl->records;
         if (f32io)
             k_scatter<float, float><<<blocks, MAP_THREADS, 0, pl->stream>>>(
-                (int)n, (const float*)pos, (const float*)q, pl->geo, pl->offsets, pl->slot, rec, pl->perm);
+                (int)n, (const float*)pos, (const float*)q, pl->geo, pl->offsets, pl->slot, hist, chunk, nbins, rec, pl->perm);
         else
             k_scatter<double, float><<<blocks, MAP_THREADS, 0, pl->stream>>>(
-                (int)n, (const double*)pos, (const double*)q, pl->geo, pl->offsets, pl->slot, rec, pl->perm);
+                (int)n, (const double*)pos, (const double*)q, pl->geo, pl->offsets, pl->slot, hist, chunk, nbins, rec, pl->perm);
     } else {
         auto* rec = (double4*)pl->records;
         if (f32io)
             k_scatter<float, double><<<blocks, MAP_THREADS, 0, pl->stream>>>(
-                (int)n, (const float*)pos, (const float*)q, pl->geo, pl->offsets, pl->slot, rec, pl->perm);
+                (int)n, (const float*)pos, (const float*)q, pl->geo, pl->offsets, pl->slot, hist, chunk, nbins, rec, pl->perm);
         else
             k_scatter<double, double><<<blocks, MAP_THREADS, 0, pl->stream>>>(
-                (int)n, (const double*)pos, (const double*)q, pl->geo, pl->offsets, pl->slot, rec, pl->perm);
+                (int)n, (const double*)pos, (const double*)q, pl->geo, pl->offsets, pl->slot, hist, chunk, nbins, rec, pl->perm);
     }
     return hipGetLastError();
 }

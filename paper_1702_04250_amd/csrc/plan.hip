@@ -108,6 +108,14 @@ pppm_status validate(const pppm_params* p, std::string& why)
     return PPPM_OK;
 }
 
+// The histogram form of the particle map needs the bins of all tiles in one
+// block's LDS.
+bool use_hist_map(const pppm_plan_s* pl, int64_t nbins)
+{
+    return pl->hist && nbins <= HIST_MAX_BINS &&
+           (size_t)nbins * sizeof(int) + LDS_STATIC <= pl->lds_limit;
+}
+
 // A tile edge B along an axis of K points is usable when the axis is a single
 // tile (B >= K), or when every tile, the last (possibly thinner) one
 // included, is at least P - 1 points thick, so that a stencil only ever
@@ -134,6 +142,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
         g.ntile[d] = (g.K[d] + g.B[d] - 1) / g.B[d];
     }
     g.ntiles = g.ntile[0] * g.ntile[1] * g.ntile[2];
+    g.bin_stride = use_hist_map(pl, (int64_t)g.ntiles * NCLASS) ? 1 : NSUB;
     const size_t lds_s = spread_lds_bytes(g, pl->rsize);
     const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize);
     const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize);
@@ -210,7 +219,7 @@ void release(pppm_plan_s* pl)
     if (pl->fft_inv) rocfft_plan_destroy(pl->fft_inv);
     if (pl->fft_inv1) rocfft_plan_destroy(pl->fft_inv1);
     if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
-    void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart,
+    void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart, pl->hist,
                     pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags,
                     pl->fft_work};
     for (void* b : bufs)
@@ -390,7 +399,9 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->G, pl->nspec * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->epart, 2048 * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
+        (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->hist, (size_t)HIST_MAX_BLOCKS * (max_bins < HIST_MAX_BINS ? max_bins : HIST_MAX_BINS) *
+                                         sizeof(int))) != PPPM_OK)
         return bail(st);
 
     e = hipMemsetAsync(pl->count, 0, max_sub * sizeof(int), pl->stream);

@@ -23,6 +23,13 @@ constexpr int NCLASS = 8;
 // less contention.  The sub-bins of a bin are adjacent in the binned order:
 // bin b starts at offsets[b * NSUB].
 constexpr int NSUB = 16;
+// Histogram form of the particle map (used when a tile's bins fit in LDS):
+// HIST_THREADS-thread blocks each bin a chunk of consecutive charges in an
+// LDS histogram and rank them there, so no device-scope atomics are needed.
+constexpr int HIST_THREADS = 1024;
+constexpr int HIST_MAX_BINS = 32768;   // LDS ints of one block
+constexpr int HIST_MAX_BLOCKS = 256;
+constexpr int HIST_CHUNK = 2048;       // target charges per block
 constexpr int MAP_THREADS = 256;
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 4;  // counts per thread per scan block
@@ -40,6 +47,7 @@ struct MapGeo {
     int ntiles;
     int halo;         // P - 1
     int check_finite;
+    int bin_stride;   // offsets entries per bin: 1 (histogram map) or NSUB (atomic map)
 };
 
 struct LaunchCfg {
@@ -85,6 +93,10 @@ struct pppm_plan_s {
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;
     int64_t qpart_blocks = 0;
+    int* hist = nullptr;       // [HIST_MAX_BLOCKS * min(max_bins, HIST_MAX_BINS)] per-block bin counts,
+                               // then per-block offsets within each bin
+    int hist_blocks = 0;       // blocks of the last histogram map
+    int hist_chunk = 0;        // charges per block of the last histogram map
     int64_t epart_blocks = 0;
 
     rocfft_plan fft_fwd = nullptr;   // D2Z of rho

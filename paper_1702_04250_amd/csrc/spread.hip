@@ -90,7 +90,7 @@ __global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
     // of them; its record is loaded before the accumulator is cleared.
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
-    const int own0 = a.offsets[tile * NCLASS * NSUB], own1 = a.offsets[(tile + 1) * NCLASS * NSUB];
+    const int own0 = a.offsets[tile * NCLASS * g.bin_stride], own1 = a.offsets[(tile + 1) * NCLASS * g.bin_stride];
     RT cur{};
     if (own0 + (int)threadIdx.x < own1) cur = rec[own0 + threadIdx.x];
 

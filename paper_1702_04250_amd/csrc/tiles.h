@@ -75,8 +75,8 @@ __device__ __forceinline__ void build_run_table(const MapGeo& g, const int (&t)[
         }
         if (active) {
             const int nb = (tn[2] * g.ntile[1] + tn[1]) * g.ntile[0] + tn[0];
-            start = offsets[(nb * NCLASS + run_first(r)) * NSUB];
-            cnt = offsets[(nb * NCLASS + run_last(r)) * NSUB] - start;
+            start = offsets[(nb * NCLASS + run_first(r)) * g.bin_stride];
+            cnt = offsets[(nb * NCLASS + run_last(r)) * g.bin_stride] - start;
         }
     }
     const int inc = wave_inclusive_scan(cnt);

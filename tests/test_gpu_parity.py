@@ -248,3 +248,26 @@ def test_separate_steps_match_compute():
     assert rho_err(rho.cpu().numpy(), ra.cpu().numpy()) < 1e-6
     assert abs(float(e) - float(ea)) < 1e-9 * abs(float(ea))
     plan.close()
+
+
+@pytest.mark.parametrize("tile", [(4, 4, 4), (8, 4, 4)])
+def test_atomic_particle_map_form(tile):
+    # tiles this fine give more bins than one block's LDS histogram holds, so
+    # the particle map takes its device-atomic form
+    w = W.config(3, order=5)
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                  launch={0: (tile, 256), 1: (tile, 256)}, label=f"atomic map {tile}")
+
+
+def test_tile_finer_than_bin_arrays_is_refused():
+    w = W.config(3, order=2)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 2, w.g_ewald, 1.0, "ad", "mixed", torch.float32, 16)
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.set_launch(0, (1, 1, 1), 256)
+    assert ei.value.status == -1
+    # the plan keeps its previous geometry and still works
+    pos = torch.rand((16, 3), dtype=torch.float32, device="cuda:0") * 170.0
+    q = torch.ones(16, dtype=torch.float32, device="cuda:0")
+    plan.compute(pos, q)
+    plan.sync()
+    plan.close()
