@@ -39,6 +39,7 @@ struct GatherArgs {
     double self_coef;    // 2 C g / sqrt(pi)
     double bg_coef;      // C pi / (V g^2)
     int vec_stage;       // tile origins and K_x allow 16-byte staging loads
+    int sort_off;        // byte offset of the lane-assignment buffers in LDS
 };
 
 template <typename R> struct Vec16;
@@ -65,17 +66,12 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     const int nsl = plane * (g.B[2] + P - 1);  // one staged mesh
     const R* __restrict__ fg = (const R*)a.field;
 
-    // The thread's first charge is loaded before the field is staged, and its
-    // stencil evaluated while the staging loads are in flight.
+    // The thread's first charge is loaded before the field is staged.
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
-    int p = first + threadIdx.x;
     RT pr{};
     int iu = 0;
-    if (p < last) {
-        pr = rec[p];
-        iu = a.perm[p];
-    }
+    if (first + (int)threadIdx.x < last) pr = rec[first + threadIdx.x];
 
     // stage tile + upper halo of every field mesh (periodic wrap)
     if (a.vec_stage) {
@@ -160,100 +156,134 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
         Q = a.eterms[4];
     }
 
+    // Lane assignment.  A wavefront's LDS reads address the same offset from
+    // 64 different stencil starts; when the starts fall in distinct LDS banks
+    // the reads are conflict-free.  Each chunk of the tile's charges is
+    // counting-sorted by the bank of its stencil start, and sorted position k
+    // goes to wavefront k % nw, lane k / nw: each wavefront gets every nw-th
+    // key in sorted order, i.e. starts spread over all banks.
+    int* sidx = (int*)(smem_raw + a.sort_off);  // [blockDim] sorted charge positions
+    int* khist = sidx + blockDim.x;              // [64] bank histogram, then its prefix
+    constexpr int KEYS = sizeof(R) == 4 ? 64 : 32;  // banks spanned by distinct starts
+
     int l[3] = {0, 0, 0};
     R w[3][P], dw[3][P];
-    auto prep = [&]() {
-        const R tt[3] = {pr.x, pr.y, pr.z};
+    for (int c0 = first; c0 < last; c0 += blockDim.x) {
+        const int cnt = min((int)blockDim.x, last - c0);
+        const bool have = (int)threadIdx.x < cnt;
+        if (c0 != first && have) pr = rec[c0 + threadIdx.x];
+        int key = 0;
+        if (have) {
+            const R tt[3] = {pr.x, pr.y, pr.z};
+            int s3[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            R f;
-            decode_local<R>(tt[d], ext[d], l[d], f);  // own charge: start in [0, ext)
-            bspline<P, R, DERIV>(f, w[d], dw[d]);
+            for (int d = 0; d < 3; ++d) {
+                R f;
+                decode_local<R>(tt[d], ext[d], s3[d], f);
+            }
+            key = (s3[2] * plane + s3[1] * a.pitch_x + s3[0]) & (KEYS - 1);
         }
-    };
-    if (p < last) prep();
-    __syncthreads();
-
-    while (p < last) {
-        const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
-        R o0 = R(0), o1 = R(0), o2 = R(0), o3 = R(0);
-        // z planes in a rolled loop: the plane's z coefficients are always
-        // element 0 of the register arrays, which shift down one per plane
-        // (no dynamic register indexing, P^2 loads in flight at most).
-#pragma unroll 1
-        for (int jz = 0; jz < P; ++jz) {
-            R p0 = R(0), p1 = R(0), p2 = R(0);
-            const R* pl0 = base + jz * plane;
+        if (threadIdx.x < 64) khist[threadIdx.x] = 0;
+        __syncthreads();  // also completes the staging of the first chunk
+        const int rank = have ? atomicAdd(&khist[key], 1) : 0;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int v = khist[threadIdx.x];
+            khist[threadIdx.x] = wave_inclusive_scan(v) - v;
+        }
+        __syncthreads();
+        if (have) sidx[khist[key] + rank] = c0 + (int)threadIdx.x;
+        __syncthreads();
+        const int nw = (cnt + 63) >> 6;
+        const int k = (threadIdx.x & 63) * nw + (int)(threadIdx.x >> 6);
+        if ((int)(threadIdx.x >> 6) < nw && k < cnt) {
+            const int pc = sidx[k];
+            pr = rec[pc];
+            iu = a.perm[pc];
+            {
+                const R tt[3] = {pr.x, pr.y, pr.z};
 #pragma unroll
-            for (int jy = 0; jy < P; ++jy) {
-                const R* row = pl0 + jy * a.pitch_x;
-                if (MODE == GATHER_IK) {
-                    R rx = R(0), ry = R(0), rz = R(0);
-#pragma unroll
-                    for (int jx = 0; jx < P; ++jx) {
-                        rx += w[0][jx] * row[jx];
-                        ry += w[0][jx] * row[nsl + jx];
-                        rz += w[0][jx] * row[2 * nsl + jx];
-                    }
-                    p0 += w[1][jy] * rx;
-                    p1 += w[1][jy] * ry;
-                    p2 += w[1][jy] * rz;
-                } else {
-                    R r0 = R(0), r1 = R(0);
-#pragma unroll
-                    for (int jx = 0; jx < P; ++jx) {
-                        const R phi = row[jx];
-                        r0 += w[0][jx] * phi;
-                        r1 += dw[0][jx] * phi;
-                    }
-                    p0 += w[1][jy] * r1;   // -> d/dx
-                    p1 += dw[1][jy] * r0;  // -> d/dy
-                    p2 += w[1][jy] * r0;   // -> d/dz and the potential
+                for (int d = 0; d < 3; ++d) {
+                    R f;
+                    decode_local<R>(tt[d], ext[d], l[d], f);  // own charge: start in [0, ext)
+                    bspline<P, R, DERIV>(f, w[d], dw[d]);
                 }
             }
-            const R wz = w[2][0], dwz = dw[2][0];
-            if (MODE == GATHER_IK) {
-                o0 += wz * p0;
-                o1 += wz * p1;
-                o2 += wz * p2;
-            } else {
-                o0 += wz * p0;
-                o1 += wz * p1;
-                o2 += dwz * p2;
-                o3 += wz * p2;
-            }
+            const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
+            R o0 = R(0), o1 = R(0), o2 = R(0), o3 = R(0);
+            // z planes in a rolled loop: the plane's z coefficients are always
+            // element 0 of the register arrays, which shift down one per plane
+            // (no dynamic register indexing, P^2 loads in flight at most).
+#pragma unroll 1
+            for (int jz = 0; jz < P; ++jz) {
+                R p0 = R(0), p1 = R(0), p2 = R(0);
+                const R* pl0 = base + jz * plane;
 #pragma unroll
-            for (int j = 0; j < P - 1; ++j) {
-                w[2][j] = w[2][j + 1];
-                if (DERIV) dw[2][j] = dw[2][j + 1];
+                for (int jy = 0; jy < P; ++jy) {
+                    const R* row = pl0 + jy * a.pitch_x;
+                    if (MODE == GATHER_IK) {
+                        R rx = R(0), ry = R(0), rz = R(0);
+#pragma unroll
+                        for (int jx = 0; jx < P; ++jx) {
+                            rx += w[0][jx] * row[jx];
+                            ry += w[0][jx] * row[nsl + jx];
+                            rz += w[0][jx] * row[2 * nsl + jx];
+                        }
+                        p0 += w[1][jy] * rx;
+                        p1 += w[1][jy] * ry;
+                        p2 += w[1][jy] * rz;
+                    } else {
+                        R r0 = R(0), r1 = R(0);
+#pragma unroll
+                        for (int jx = 0; jx < P; ++jx) {
+                            const R phi = row[jx];
+                            r0 += w[0][jx] * phi;
+                            r1 += dw[0][jx] * phi;
+                        }
+                        p0 += w[1][jy] * r1;   // -> d/dx
+                        p1 += dw[1][jy] * r0;  // -> d/dy
+                        p2 += w[1][jy] * r0;   // -> d/dz and the potential
+                    }
+                }
+                const R wz = w[2][0], dwz = dw[2][0];
+                if (MODE == GATHER_IK) {
+                    o0 += wz * p0;
+                    o1 += wz * p1;
+                    o2 += wz * p2;
+                } else {
+                    o0 += wz * p0;
+                    o1 += wz * p1;
+                    o2 += dwz * p2;
+                    o3 += wz * p2;
+                }
+#pragma unroll
+                for (int j = 0; j < P - 1; ++j) {
+                    w[2][j] = w[2][j + 1];
+                    if (DERIV) dw[2][j] = dw[2][j + 1];
+                }
+            }
+            TO* out = (TO*)a.out0;
+            const R qv = pr.w;
+            if (MODE == GATHER_IK) {
+                out[3 * (size_t)iu + 0] = (TO)(qv * o0);
+                out[3 * (size_t)iu + 1] = (TO)(qv * o1);
+                out[3 * (size_t)iu + 2] = (TO)(qv * o2);
+            } else if (MODE == GATHER_AD) {
+                out[3 * (size_t)iu + 0] = (TO)(-qv * o0 * (R)a.inv_h[0]);
+                out[3 * (size_t)iu + 1] = (TO)(-qv * o1 * (R)a.inv_h[1]);
+                out[3 * (size_t)iu + 2] = (TO)(-qv * o2 * (R)a.inv_h[2]);
+            } else {
+                const double qd = (double)qv;
+                if (out) {
+                    out[3 * (size_t)iu + 0] = (TO)(gE * qd * (double)o0 * a.inv_h[0]);
+                    out[3 * (size_t)iu + 1] = (TO)(gE * qd * (double)o1 * a.inv_h[1]);
+                    out[3 * (size_t)iu + 2] = (TO)(gE * qd * (double)o2 * a.inv_h[2]);
+                }
+                if (a.out1)
+                    ((TO*)a.out1)[iu] = (TO)(gE * ((double)o3 - a.self_coef * qd - a.bg_coef * Q));
             }
         }
-        TO* out = (TO*)a.out0;
-        const R qv = pr.w;
-        if (MODE == GATHER_IK) {
-            out[3 * (size_t)iu + 0] = (TO)(qv * o0);
-            out[3 * (size_t)iu + 1] = (TO)(qv * o1);
-            out[3 * (size_t)iu + 2] = (TO)(qv * o2);
-        } else if (MODE == GATHER_AD) {
-            out[3 * (size_t)iu + 0] = (TO)(-qv * o0 * (R)a.inv_h[0]);
-            out[3 * (size_t)iu + 1] = (TO)(-qv * o1 * (R)a.inv_h[1]);
-            out[3 * (size_t)iu + 2] = (TO)(-qv * o2 * (R)a.inv_h[2]);
-        } else {
-            const double qd = (double)qv;
-            if (out) {
-                out[3 * (size_t)iu + 0] = (TO)(gE * qd * (double)o0 * a.inv_h[0]);
-                out[3 * (size_t)iu + 1] = (TO)(gE * qd * (double)o1 * a.inv_h[1]);
-                out[3 * (size_t)iu + 2] = (TO)(gE * qd * (double)o2 * a.inv_h[2]);
-            }
-            if (a.out1)
-                ((TO*)a.out1)[iu] = (TO)(gE * ((double)o3 - a.self_coef * qd - a.bg_coef * Q));
-        }
-        p += blockDim.x;
-        if (p < last) {
-            pr = rec[p];
-            iu = a.perm[p];
-            prep();
-        }
+        __syncthreads();  // the sort buffers are reused by the next chunk
     }
 }
 
@@ -286,9 +316,18 @@ hipError_t dispatch_types(const pppm_plan_s* pl, dim3 grid, dim3 block, size_t l
 
 }  // namespace
 
+// LDS of the staged field meshes (tile + upper halo), rounded up to 16 bytes.
+size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
+{
+    const size_t b = (size_t)ncomp * (g.B[0] + order - 1) * (g.B[1] + order - 1) * (g.B[2] + order - 1) * elem_bytes;
+    return (b + 15) & ~(size_t)15;
+}
+
+// Total LDS of a gather launch at the largest workgroup (512 threads): the
+// staged meshes plus the lane-assignment buffers.
 size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
 {
-    return (size_t)ncomp * (g.B[0] + order - 1) * (g.B[1] + order - 1) * (g.B[2] + order - 1) * elem_bytes;
+    return gather_field_lds_bytes(g, order, ncomp, elem_bytes) + (512 + 64) * sizeof(int);
 }
 
 hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy)
@@ -317,17 +356,20 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     const int vw = 16 / (int)rs;
     a.vec_stage = (pl->geo.K[0] % vw == 0) && (pl->geo.B[0] % vw == 0);
     dim3 grid(pl->geo.ntiles), block(c.threads);
+    const int nc = mode == GATHER_IK ? 3 : 1;
+    a.sort_off = (int)gather_field_lds_bytes(pl->geo, P, nc, rs);
+    const size_t lds = a.sort_off + (size_t)(c.threads + 64) * sizeof(int);
     switch (mode) {
     case GATHER_IK:
         a.field = pl->field;
-        return dispatch_types<GATHER_IK>(pl, grid, block, gather_lds_bytes(pl->geo, P, 3, rs), a);
+        return dispatch_types<GATHER_IK>(pl, grid, block, lds, a);
     case GATHER_AD:
         a.field = pl->field;
-        return dispatch_types<GATHER_AD>(pl, grid, block, gather_lds_bytes(pl->geo, P, 1, rs), a);
+        return dispatch_types<GATHER_AD>(pl, grid, block, lds, a);
     default:
         // phi lives after the three field meshes for ik plans, first for ad plans
         a.field = (const char*)pl->field + (pl->p.diff == PPPM_DIFF_IK ? 3 * pl->ncell * rs : 0);
-        return dispatch_types<GATHER_ADJOINT>(pl, grid, block, gather_lds_bytes(pl->geo, P, 1, rs), a);
+        return dispatch_types<GATHER_ADJOINT>(pl, grid, block, lds, a);
     }
 }
 

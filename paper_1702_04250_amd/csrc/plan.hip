@@ -43,7 +43,7 @@ pppm_status fail(pppm_plan_s* pl, pppm_status st, const std::string& msg)
 
 constexpr int64_t MAX_CELLS = int64_t(1) << 30;
 constexpr int MAX_MESH = 2048;
-constexpr size_t LDS_PREFERRED = 64 * 1024 - 1024;  // keeps several workgroups per CU
+constexpr size_t LDS_PREFERRED = 80 * 1024 - 1024;  // keeps two or more workgroups per CU
 constexpr size_t LDS_STATIC = 1024;                 // static LDS of the kernels, rounded up
 
 std::once_flag g_fft_once;

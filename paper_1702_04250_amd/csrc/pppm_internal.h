@@ -133,6 +133,7 @@ hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);
 // LDS bytes a kernel needs for the plan's tile shape.
 size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes);
 size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
+size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 
 enum GatherMode { GATHER_IK = 0, GATHER_AD = 1, GATHER_ADJOINT = 2 };
 
