@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-PROFILE = os.path.join(ROOT, "profiles", "k_spread_c3_p5_mixed_ad.md")
+PROFILE = os.path.join(ROOT, "profiles", "step_kernels_uniform524k_K128_P5_ad_mixed.md")
 # kernel symbol of each timed step (one launch per call)
 STEP_KERNEL = {"make_rho": "k_spread", "fieldforce_ad": "k_gather"}
 METRIC = "particles/s for make_rho+fieldforce (ik & ad) at P=5; % HBM peak; FP32 vs FP64 error"

@@ -183,8 +183,9 @@ const char *pppm_last_error(pppm_plan plan);
  * binning, spread and gather kernels of the plan, so changing it discards the
  * mapped particles (call pppm_particle_map or pppm_compute again).  Every
  * tile must be at least order - 1 points thick along an axis that has more
- * than one tile.  threads = workgroup size (64..512, multiple of 64) of the
- * kernel `which`: 0 = spread, 1 = gather (forward), 2 = gather (adjoint).
+ * than one tile.  threads = workgroup size of the kernel `which`, a multiple
+ * of 64: 0 = spread (64..1024), 1 = gather, forward (64..512), 2 = gather,
+ * adjoint (64..512).
  * Returns PPPM_ERR_ARG (and changes nothing) for an unusable geometry,
  * including one whose shared memory exceeds the device limit. */
 pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t *tile, int32_t threads);

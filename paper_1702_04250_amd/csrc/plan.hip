@@ -418,7 +418,8 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     }
     if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
 
-    pl->spread_cfg.threads = pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;
+    pl->spread_cfg.threads = 1024;
+    pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;
     {
         std::string bad = default_tile(pl);
         if (!bad.empty()) {
@@ -562,8 +563,10 @@ pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t* t
     pppm_status st = check_plan(plan);
     if (st != PPPM_OK) return st;
     if (which < 0 || which > 2 || !tile) return fail(plan, PPPM_ERR_ARG, "which must be 0, 1 or 2 and tile non-NULL");
-    if (threads < 64 || threads > 512 || threads % 64)
-        return fail(plan, PPPM_ERR_ARG, "threads must be a multiple of 64 in [64, 512]");
+    const int max_threads = which == 0 ? 1024 : 512;  // the kernels' launch bounds
+    if (threads < 64 || threads > max_threads || threads % 64)
+        return fail(plan, PPPM_ERR_ARG, "threads must be a multiple of 64 in [64, " + std::to_string(max_threads) +
+                                            "] (1024 for make_rho, 512 for the gathers)");
     const MapGeo keep = plan->geo;
     const int64_t keep_bins = plan->nbins;
     const Stage keep_stage = plan->stage;

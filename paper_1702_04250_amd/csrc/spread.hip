@@ -73,7 +73,7 @@ template <> struct Acc<double> {
 };
 
 template <int P, typename R, typename A>
-__global__ __launch_bounds__(512) void k_spread(SpreadArgs a)
+__global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ RunTable rt;

@@ -145,7 +145,7 @@ def test_charged_system_background_term():
 
 
 @pytest.mark.parametrize("which,tile,threads", [
-    (0, (8, 8, 8), 128), (0, (16, 8, 4), 64), (0, (32, 16, 8), 512), (0, (4, 4, 4), 256),
+    (0, (8, 8, 8), 128), (0, (16, 8, 4), 64), (0, (32, 16, 8), 512), (0, (4, 4, 4), 256), (0, (64, 16, 8), 1024),
     (1, (8, 8, 8), 128), (1, (16, 16, 4), 512), (1, (4, 8, 16), 64), (1, (32, 8, 8), 256),
 ])
 @pytest.mark.parametrize("diff", ["ik", "ad"])
@@ -257,6 +257,18 @@ def test_atomic_particle_map_form(tile):
     w = W.config(3, order=5)
     run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
                   launch={0: (tile, 256), 1: (tile, 256)}, label=f"atomic map {tile}")
+
+
+def test_gather_workgroup_limit():
+    w = W.config(1)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", "mixed", torch.float32, w.n)
+    for which in (1, 2):
+        with pytest.raises(pkg.PPPMError) as ei:
+            plan.set_launch(which, (8, 8, 8), 1024)
+        assert ei.value.status == -1
+    plan.set_launch(0, (8, 8, 8), 1024)  # make_rho takes up to 1024 threads
+    assert plan.get_launch(0)[1] == 1024
+    plan.close()
 
 
 def test_tile_finer_than_bin_arrays_is_refused():
