@@ -1,8 +1,9 @@
 """Benchmark of the PPPM particle-mesh hot path on one MI355X.
 
 Workload: 524,288 charges (+-1, exactly neutral) uniform in a 170 A cube,
-mesh 128^3, order P = 5, ad differentiation, mixed precision (FP32
-stencils/LDS/gathers, FP64 mesh charge and energy), FP32 particle arrays.
+mesh 128^3, order P = 5, ad differentiation, mixed precision (FP32 stencils,
+exact fixed-point LDS sums, FP32 gathers and FFTs, FP64 mesh flush and energy),
+FP32 particle arrays.
 
 One step = one full forward evaluation through the C ABI: particle map
 (binning), make_rho, Poisson (rocFFT + influence function + FP64 energy),
@@ -319,7 +320,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}-P{order}: {w.notes}", "n": n, "mesh": list(w.mesh), "order": order,
-                   "diff": "ad", "prec": "mixed (f32 stencils/LDS/gathers, f64 mesh charge, FFT-forward and energy)",
+                   "diff": "ad", "prec": "mixed (f32 stencils, LDS fixed-point sums, gathers and FFTs; f64 mesh flush and energy)",
                    "io_dtype": "f32", "step": "particle_map + make_rho + poisson + fieldforce"},
         "roofline": {"bound": "hbm", "kernel": STEP_KERNEL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(STEP_KERNEL[dom]),

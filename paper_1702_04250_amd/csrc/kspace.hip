@@ -83,7 +83,7 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_influence(KGeo kg, long long
 // counts the Hermitian partner of each half-spectrum point.
 template <typename C>
 __global__ __launch_bounds__(KSPACE_THREADS) void k_solve(KGeo kg, long long nspec, int mode,
-                                                           const double2* __restrict__ rho_hat,
+                                                           const C* __restrict__ rho_hat,
                                                            const double* __restrict__ G, C* __restrict__ spec,
                                                            double* __restrict__ epart)
 {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_solve(KGeo kg, long long nsp
     for (long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x; idx < nspec;
          idx += (long long)gridDim.x * KSPACE_THREADS) {
         const int ix = (int)(idx % kg.nxh);
-        const double2 rh = rho_hat[idx];
+        const double2 rh = make_double2((double)rho_hat[idx].x, (double)rho_hat[idx].y);
         const double gk = G[idx];
         const bool edge = (ix == 0) || (2 * ix == kg.K[0]);
         e += (edge ? 0.5 : 1.0) * gk * (rh.x * rh.x + rh.y * rh.y);
@@ -125,14 +125,14 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_solve(KGeo kg, long long nsp
 
 // phi_hat only, into the slot after the ik field spectra (adjoint of ik plans).
 template <typename C>
-__global__ __launch_bounds__(KSPACE_THREADS) void k_phi_only(long long nspec, const double2* __restrict__ rho_hat,
+__global__ __launch_bounds__(KSPACE_THREADS) void k_phi_only(long long nspec, const C* __restrict__ rho_hat,
                                                               const double* __restrict__ G, C* __restrict__ out)
 {
     for (long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x; idx < nspec;
          idx += (long long)gridDim.x * KSPACE_THREADS) {
-        const double2 rh = rho_hat[idx];
+        const double rx = (double)rho_hat[idx].x, ry = (double)rho_hat[idx].y;
         const double gk = G[idx];
-        store_c(out + idx, gk * rh.x, gk * rh.y);
+        store_c(out + idx, gk * rx, gk * ry);
     }
 }
 
@@ -221,7 +221,7 @@ hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only)
         const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
         void* out = (char*)pl->spec + 3 * pl->nspec * csz;
         if (pl->mixed)
-            k_phi_only<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(pl->nspec, (const double2*)pl->rho_hat,
+            k_phi_only<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(pl->nspec, (const float2*)pl->rho_hat,
                                                                            pl->G, (float2*)out);
         else
             k_phi_only<double2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(pl->nspec, (const double2*)pl->rho_hat,
@@ -231,7 +231,7 @@ hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only)
     pl->epart_blocks = blocks;
     const int mode = (pl->p.diff == PPPM_DIFF_AD) ? 1 : 0;
     if (pl->mixed)
-        k_solve<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, mode, (const double2*)pl->rho_hat,
+        k_solve<float2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, mode, (const float2*)pl->rho_hat,
                                                                     pl->G, (float2*)pl->spec, pl->epart);
     else
         k_solve<double2><<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, mode, (const double2*)pl->rho_hat,

@@ -231,9 +231,10 @@ pppm_status make_fft_plans(pppm_plan_s* pl)
     std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
     FFT_TRY(pl, g_fft_setup);
     const size_t lengths[3] = {(size_t)pl->geo.K[0], (size_t)pl->geo.K[1], (size_t)pl->geo.K[2]};
+    // the mixed form transforms in FP32 both ways; the energy sum stays FP64
     const rocfft_precision inv_prec = pl->mixed ? rocfft_precision_single : rocfft_precision_double;
     FFT_TRY(pl, rocfft_plan_create(&pl->fft_fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
-                                   rocfft_precision_double, 3, lengths, 1, nullptr));
+                                   inv_prec, 3, lengths, 1, nullptr));
     FFT_TRY(pl, rocfft_plan_create(&pl->fft_inv, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
                                    inv_prec, 3, lengths, (size_t)pl->ncomp, nullptr));
     if (pl->p.diff == PPPM_DIFF_IK)
@@ -392,8 +393,8 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->qpart, 3 * map_blocks * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->rho, pl->ncell * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->rho_hat, pl->nspec * sizeof(double2))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho, pl->ncell * pl->rsize)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho_hat, pl->nspec * csz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->nspec * csz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->field, (pl->ncomp + 1) * pl->ncell * pl->rsize)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->G, pl->nspec * sizeof(double))) != PPPM_OK ||

@@ -82,8 +82,8 @@ struct pppm_plan_s {
                                // t = stencil start within the tile + fraction
     int* perm = nullptr;       // [max_particles] binned position -> caller index
     double* qpart = nullptr;   // [3 * map blocks] per block: sum q, sum q^2, max |q|
-    double* rho = nullptr;     // [ncell] mesh charge, FFT input
-    void* rho_hat = nullptr;   // [nspec] complex double
+    void* rho = nullptr;       // [ncell] mesh charge of type R (FP32 in the mixed form), FFT input
+    void* rho_hat = nullptr;   // [nspec] complex R
     void* spec = nullptr;      // [(ncomp + 1) * nspec] complex R: field spectra, then phi spectrum
     void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
     double* G = nullptr;       // [nspec] (C / V) G(k)

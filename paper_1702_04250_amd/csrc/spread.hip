@@ -7,7 +7,7 @@
 // sub-bricks up to P - 1 points below it - and adds the part of each stencil
 // that falls inside the tile with LDS atomics.  Every mesh point is owned by
 // exactly one tile, so the tile is flushed to the global mesh with plain
-// coalesced FP64 stores: no global atomics and no zero-fill of the mesh.
+// coalesced stores: no global atomics and no zero-fill of the mesh.
 // This is the GPU counterpart of the paper's per-thread private grids
 // ("rethread"): privatise, accumulate, then combine - here the combine is a
 // disjoint ownership of the output.
@@ -22,7 +22,10 @@
 // correct whenever the final value fits, |rho_m| 2^e < 2^31.  e is chosen per
 // tile from a bound on any of its points: each charge read by the tile adds
 // at most max|q| wmax(P)^3 to a point, with one bit of headroom.  The flush
-// converts to FP64.  The FP64 form accumulates with ds_add_f64.
+// converts each exact sum to FP64; that value goes to the caller's FP64 mesh
+// when one is asked for, and, rounded to FP32, to the plan's FFT input (the
+// mixed form transforms in FP32).  The FP64 form accumulates with ds_add_f64
+// and keeps an FP64 FFT input.
 #include "tiles.h"
 
 namespace pppm {
@@ -33,8 +36,8 @@ struct SpreadArgs {
     MapGeo g;
     const int* offsets;
     const void* rec;
-    double* rho;
-    double* rho_user;
+    void* rho;            // plan mesh of type R (the FFT input)
+    double* rho_user;     // caller's FP64 mesh or null
     const double* stats;  // [1] max |q|
     int pitch_x;          // LDS row pitch (points): B_x + 2 (P - 1)
     int rows_y;           // LDS rows per plane: B_y, + P - 1 on a single-tile axis
@@ -201,14 +204,14 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
         __syncthreads();
     }
 
-    // flush: every point of the tile is owned here; coalesced FP64 stores
+    // flush: every point of the tile is owned here; coalesced stores
     const int ex = ext[0], ey = ext[1], ez = ext[2];
     const int npts = ex * ey * ez;
     for (int i = threadIdx.x; i < npts; i += blockDim.x) {
         const int lx = i % ex, ly = (i / ex) % ey, lz = i / (ex * ey);
         const double v = ldexp((double)acc[lz * plane + ly * pitch + H + lx], -e);
         const size_t gidx = ((size_t)(T0[2] + lz) * g.K[1] + (T0[1] + ly)) * g.K[0] + (T0[0] + lx);
-        a.rho[gidx] = v;
+        ((R*)a.rho)[gidx] = (R)v;
         if (a.rho_user) a.rho_user[gidx] = v;
     }
 }
