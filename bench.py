@@ -184,8 +184,11 @@ class Timer:
         return 1e3 * statistics.fmean(a.elapsed_time(b) for a, b in self.pairs[label])
 
 
-def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False):
-    """Warm up, then time exactly `steps` full forward steps (and backward if asked)."""
+def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False, flush=None):
+    """Warm up, then time exactly `steps` full forward steps (and backward if asked).
+
+    flush: optional device buffer overwritten before each timed step (outside
+    the timed events) to evict the L2 and MALL caches."""
     stream = plan.stream
     dev = plan.device
     n = pos.shape[0]
@@ -208,6 +211,7 @@ def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False):
             plan.energy_backward(ge, pos, q)
         e5 = t.mark() if t else None
         if t:
+            t.add("step", e0, e4)
             t.add("particle_map", e0, e1)
             t.add("make_rho", e1, e2)
             t.add("poisson", e2, e3)
@@ -223,6 +227,8 @@ def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False):
         start = timer.mark()
         t0 = time.perf_counter()
         for _ in range(steps):
+            if flush is not None:
+                flush.add_(1.0)
             step(timer)
         end = timer.mark()
         torch.cuda.synchronize()
@@ -231,6 +237,8 @@ def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False):
     res = {"ms_per_step": total_ms / steps, "wall_ms_per_step": 1e3 * wall / steps}
     for k in timer.pairs:
         res[k + "_us"] = timer.mean_us(k)
+    per_step = sorted(1e3 * a.elapsed_time(b) for a, b in timer.pairs["step"])
+    res["step_us_p10_p50_p90"] = [float(np.percentile(per_step, p)) for p in (10, 50, 90)]
     return res, forces, energy
 
 
@@ -326,6 +334,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(STEP_KERNEL[dom]),
                      "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom},
         "kernels_us": {k[:-3]: v for k, v in head.items() if k.endswith("_us") and k != "wall_ms_per_step"},
+        "step_us_p10_p50_p90": head["step_us_p10_p50_p90"],
         "make_rho_fieldforce": {
             "ad": {"us": t_rho + t_ff, "particles_per_s": n / ((t_rho + t_ff) * 1e-6),
                    "hbm_frac": (b_rho + b_ff) / ((t_rho + t_ff) * 1e-6) / 1e9 / HBM_PEAK_GBS},
@@ -352,6 +361,25 @@ def main():
                             "kernels_us": {k[:-3]: v for k, v in r64.items() if k.endswith("_us")},
                             "make_rho_fieldforce_particles_per_s":
                                 n / ((r64["make_rho_us"] + r64["fieldforce_us"]) * 1e-6)}
+        # cold caches: a 512 MiB buffer is rewritten before each timed step
+        flush = torch.zeros(128 << 20, dtype=torch.float32, device=dev)
+        cold, _, _ = run_loop(torch, plan_ad, pos, q, min(args.steps, 20), args.warmup, "ad", flush=flush)
+        out["cold_cache"] = {"note": "512 MiB written to HBM before each step (untimed), evicting L2 and MALL",
+                             "ms_per_step": cold["ms_per_step"],
+                             "kernels_us": {k[:-3]: v for k, v in cold.items() if k.endswith("_us")}}
+        del flush
+        # non-uniform load: the same charges packed into half the box
+        wi = workloads.interfacial(order)
+        pos_i = torch.tensor(wi.pos, dtype=torch.float32, device=dev).contiguous()
+        q_i = torch.tensor(wi.q, dtype=torch.float32, device=dev).contiguous()
+        plan_i = pkg.Plan(wi.box_lo, wi.box_len, wi.mesh, order, wi.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                          max_particles=wi.n, device=dev, stream=stream)
+        ri, _, _ = run_loop(torch, plan_i, pos_i, q_i, args.steps, args.warmup, "ad")
+        out["interfacial"] = {"workload": f"{wi.name}: {wi.notes}", "ms_per_step": ri["ms_per_step"],
+                              "kernels_us": {k[:-3]: v for k, v in ri.items() if k.endswith("_us")},
+                              "make_rho_fieldforce_particles_per_s":
+                                  wi.n / ((ri["make_rho_us"] + ri["fieldforce_us"]) * 1e-6)}
+        plan_i.close()
         # forward + energy backward (autograd form), mixed
         rb, _, _ = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad", backward=True)
         out["forward_backward"] = {"ms_per_step": rb["ms_per_step"], "backward_us": rb["backward_us"],

@@ -8,15 +8,22 @@
 namespace pppm {
 
 // Number of XCDs (chiplets, each with its own L2) of an MI355X.  Workgroups
-// are handed to XCDs round-robin; remapping gives each XCD one contiguous
-// slab of tiles so neighbouring tiles share halo data in the same L2.
+// are handed to XCDs round-robin (workgroup i to XCD i mod 8).  The remap
+// gives each XCD runs of XCD_CHUNK consecutive tiles (neighbours along x,
+// which share halo records in that XCD's L2), and deals the runs to the XCDs
+// round-robin, so every XCD's share is spread over the whole mesh and a
+// charge density that varies across the box still loads the XCDs evenly.
+// The tail that does not fill a whole round keeps the identity order.
 constexpr int NUM_XCD = 8;
+constexpr int XCD_CHUNK = 4;
 
 __device__ __forceinline__ int xcd_remap(int wg, int nwg)
 {
-    const int q = nwg / NUM_XCD, r = nwg % NUM_XCD;
+    constexpr int ROUND = NUM_XCD * XCD_CHUNK;
+    const int nfull = nwg / ROUND * ROUND;
+    if (wg >= nfull) return wg;
     const int x = wg % NUM_XCD, local = wg / NUM_XCD;
-    return x * q + (x < r ? x : r) + local;
+    return (local / XCD_CHUNK) * ROUND + x * XCD_CHUNK + local % XCD_CHUNK;
 }
 
 // Record of a binned particle: stencil start within its tile plus the

@@ -283,3 +283,11 @@ def test_tile_finer_than_bin_arrays_is_refused():
     plan.compute(pos, q)
     plan.sync()
     plan.close()
+
+
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_interfacial_slab(diff):
+    # half the tiles empty, the rest at twice the average load
+    w = W.interfacial()
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed", torch.float32,
+                  label="interfacial")

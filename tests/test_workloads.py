@@ -67,3 +67,11 @@ def test_seeded_reproducible():
 def test_nacl_lattice():
     pos, q, L = W.nacl_lattice(8, 2.5)
     assert len(q) == 512 and L == 20.0 and q.sum() == 0
+
+
+def test_interfacial_slab():
+    w = W.interfacial()
+    assert w.n == 524288 and w.q.sum() == 0 and np.all(np.abs(w.q) == 1)
+    assert np.all(w.pos[:, 2] < 85.0) and np.all(w.pos >= 0)
+    # x and y still span the whole box
+    assert w.pos[:, 0].max() > 169.0 and w.pos[:, 1].max() > 169.0

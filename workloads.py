@@ -195,6 +195,20 @@ def config(idx: int, order: int | None = None) -> Workload:
     raise ValueError(f"no workload {idx}")
 
 
+def interfacial(order: int = 5) -> Workload:
+    """Non-uniform load: the 524,288 +-1 charges of the benchmark system packed
+    into the lower half of the box along z (a slab at twice the density, the
+    upper half vacuum), same box, mesh and split.  Half of the mesh tiles hold
+    no charge and the others twice the average."""
+    rng = np.random.default_rng(6)
+    n, length = 524288, 170.0
+    pos = rng.uniform(0.0, 1.0, size=(n, 3)) * np.array([length, length, 0.5 * length])
+    q = rng.permutation(np.concatenate([np.ones(n // 2), -np.ones(n // 2)]))
+    return Workload("interfacial-524k-L170-K128", _wrap(pos, length), q, (0.0,) * 3, (length,) * 3, (128,) * 3,
+                    order, 0.30, ("ad", "ik"), 6,
+                    "524,288 +-1 charges in the lower half (z < L/2) of a 170 A cube, vacuum above")
+
+
 def random_system(n: int, box_len, seed: int, charge: str = "gaussian", box_lo=(0.0, 0.0, 0.0)):
     """Small general test system: uniform positions in an orthorhombic box."""
     rng = np.random.default_rng(seed)
