@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the headline loop")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--shift-work", action="store_true",
+                    help="for each order P = 3..7, the coarsest mesh meeting a force-error target on the "
+                         "benchmark system, and the step time there; prints a table and exits")
     ap.add_argument("--summarize", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR "
                          "(subfolders trace, fetch, write, calib_fetch, calib_write) and exit")
@@ -267,6 +270,53 @@ def cpu_baseline(w, order, pos_r, q_r, budget_s=12.0):
     }, res
 
 
+def shift_work(torch, pkg, workloads, steps, warmup):
+    """Higher order on a coarser mesh (the paper's trade, its Section 2.3 and
+    the results of Section 4): for each P, the smallest K (of a list of FFT
+    friendly sizes) whose mixed-form ad forces are within the target RMS
+    relative error of a converged reference, and the GPU step time there.
+    Reference: the FP64 form at P = 7 on a 288^3 mesh (h = 0.59 A)."""
+    w = workloads.config(3)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    pos = torch.tensor(w.pos, dtype=torch.float32, device=dev).contiguous()
+    q = torch.tensor(w.q, dtype=torch.float32, device=dev).contiguous()
+    pos64, q64 = pos.double(), q.double()
+
+    def forces(P, K, prec, p, qq):
+        plan = pkg.Plan(w.box_lo, w.box_len, (K,) * 3, P, w.g_ewald, 1.0, "ad", prec, p.dtype,
+                        max_particles=w.n, device=dev, stream=stream)
+        with torch.cuda.stream(stream):
+            f = plan.compute(p, qq, want_energy=False)["forces"]
+        plan.sync()
+        out = f.double().cpu().numpy()
+        return plan, out
+
+    ref_plan, ref = forces(7, 288, "fp64", pos64, q64)
+    ref_plan.close()
+    den = float((ref ** 2).sum())
+    sizes = [32, 40, 48, 56, 64, 72, 80, 96, 112, 128, 144, 160, 192, 224, 256]
+    rows = []
+    for target in (1e-3, 1e-4):
+        for P in range(3, 8):
+            chosen = None
+            for K in sizes:
+                plan, f = forces(P, K, "mixed", pos, q)
+                err = float(np.sqrt(((f - ref) ** 2).sum() / den))
+                if err <= target:
+                    res, _, _ = run_loop(torch, plan, pos, q, steps, warmup, "ad")
+                    chosen = {"target": target, "P": P, "K": K, "h_A": w.box_len[0] / K, "force_err": err,
+                              "step_us": 1e3 * res["ms_per_step"],
+                              "kernels_us": {k[:-3]: round(v, 2) for k, v in res.items()
+                                             if k.endswith("_us") and k != "step_us"}}
+                    plan.close()
+                    break
+                plan.close()
+            rows.append(chosen or {"target": target, "P": P, "K": None})
+            print(json.dumps(rows[-1]), flush=True)
+    return rows
+
+
 def main():
     args = parse()
     if args.summarize:
@@ -290,6 +340,10 @@ def main():
 
     import paper_1702_04250_amd as pkg
     import workloads
+
+    if args.shift_work:
+        shift_work(torch, pkg, workloads, min(args.steps, 20), args.warmup)
+        return
 
     if not pkg.binding.LIB_PATH.exists():
         raise SystemExit("libpppm_mi355x.so is not built: run python -m paper_1702_04250_amd.build")

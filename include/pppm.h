@@ -83,9 +83,10 @@ typedef enum { PPPM_DIFF_IK = 0, PPPM_DIFF_AD = 1 } pppm_diff;
 
 /* Arithmetic of the particle-mesh steps.
  *   FP64:  every step in double precision.
- *   MIXED: stencil weights, spread (LDS accumulation) and gathers in FP32;
- *          the mesh charge is stored in FP64, the forward FFT and the energy
- *          reduction are FP64; the inverse FFTs and field meshes are FP32. */
+ *   MIXED: stencil weights and their products in FP32, summed exactly in
+ *          32-bit fixed point in LDS; each mesh point is flushed as FP64 (the
+ *          caller's rho) and as FP32 (the plan's FFT input); FFTs, field
+ *          meshes and gathers in FP32; the energy reduction in FP64. */
 typedef enum { PPPM_PREC_FP64 = 0, PPPM_PREC_MIXED = 1 } pppm_prec;
 
 /* Element type of the particle-side arrays (pos, q, forces, gradients). */
@@ -155,8 +156,10 @@ pppm_status pppm_compute(pppm_plan plan, int64_t n, const void *pos, const void 
  * with phi the mesh potential of the plan's influence function, interpolated
  * with the same stencil.  Uses the mesh kept by the last pppm_compute (or
  * pppm_poisson), which must have been called with the same pos, q and n
- * pointers and count (else PPPM_ERR_STATE).  Recomputes the stencil weights
- * from pos; either output may be NULL. */
+ * pointers and count (else PPPM_ERR_STATE), and the charges binned by that
+ * call: the stencil weights are recomputed from the binned positions of the
+ * forward step, so the gradient belongs to the positions the potential was
+ * computed for.  Either output may be NULL. */
 pppm_status pppm_energy_backward(pppm_plan plan, const double *grad_energy, int64_t n,
                                  const void *pos, const void *q, void *grad_pos, void *grad_q);
 

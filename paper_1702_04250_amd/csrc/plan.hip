@@ -156,10 +156,14 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     return "";
 }
 
-// Edge for an axis of K points near a preferred edge b: split the axis into
-// about K / b equal tiles, fewer if the last one would be thinner than P - 1.
+// Edge for an axis of K points near a preferred edge b: b itself when the
+// last tile keeps at least P - 1 points (edges that are multiples of 4 keep
+// the gather's 16-byte staging loads), else about K / b equal tiles, fewer if
+// the last one would be thinner than P - 1.
 int split_edge(int K, int b, int P)
 {
+    // the preferred edge itself when it fits (a thinner last tile is fine)
+    if (b < K && edge_ok(K, b, P)) return b;
     int n = (K + b / 2) / b;
     if (n < 1) n = 1;
     for (; n > 1; --n) {
@@ -496,11 +500,9 @@ pppm_status pppm_energy_backward(pppm_plan plan, const double* grad_energy, int6
     if (pl->stage < Stage::Solved || n != pl->n || pos != pl->pos_ptr || q != pl->q_ptr)
         return fail(pl, PPPM_ERR_STATE, "energy_backward needs a preceding compute on the same pos, q and n");
     if (n == 0 || (!grad_pos && !grad_q)) return PPPM_OK;
-    const bool phi_valid = pl->phi_valid;
-    // re-derive the binned records and stencils from the positions
-    if ((st = do_particle_map(pl, n, pos, q)) != PPPM_OK) return st;
-    pl->stage = Stage::Solved;
-    pl->phi_valid = phi_valid;
+    // The binned records of the forward call are still those of (pos, q): the
+    // adjoint gather reads them and recomputes the stencil weights, so the
+    // gradient belongs to the same positions as the retained potential.
     if (!pl->phi_valid) {
         // ik plan: the potential mesh of the same influence function
         HIP_TRY(pl, launch_kspace(pl, true));
