@@ -434,6 +434,25 @@ def main():
                               "make_rho_fieldforce_particles_per_s":
                                   wi.n / ((ri["make_rho_us"] + ri["fieldforce_us"]) * 1e-6)}
         plan_i.close()
+        # the largest system: 4,194,304 charges of water, 256^3, P = 7
+        w5 = workloads.config(5)
+        pos5 = torch.tensor(w5.pos, dtype=torch.float32, device=dev).contiguous()
+        q5 = torch.tensor(w5.q, dtype=torch.float32, device=dev).contiguous()
+        big = {"workload": f"{w5.name}: {w5.notes}"}
+        for label, diff, prec, p_, q_ in (("mixed_ad_with_backward", "ad", "mixed", pos5, q5),
+                                          ("mixed_ik", "ik", "mixed", pos5, q5),
+                                          ("fp64_ad", "ad", "fp64", pos5.double(), q5.double())):
+            plan5 = pkg.Plan(w5.box_lo, w5.box_len, w5.mesh, w5.order, w5.g_ewald, 1.0, diff, prec, p_.dtype,
+                             max_particles=w5.n, device=dev, stream=stream)
+            r5, _, _ = run_loop(torch, plan5, p_, q_, min(args.steps, 20), args.warmup, diff,
+                                backward=(label == "mixed_ad_with_backward"))
+            big[label] = {"ms_per_step": r5["ms_per_step"],
+                          "kernels_us": {k[:-3]: v for k, v in r5.items() if k.endswith("_us")},
+                          "make_rho_fieldforce_particles_per_s":
+                              w5.n / ((r5["make_rho_us"] + r5["fieldforce_us"]) * 1e-6)}
+            plan5.close()
+        out["water_4M_P7"] = big
+        del pos5, q5
         # forward + energy backward (autograd form), mixed
         rb, _, _ = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad", backward=True)
         out["forward_backward"] = {"ms_per_step": rb["ms_per_step"], "backward_us": rb["backward_us"],
