@@ -24,8 +24,10 @@
 // at most max|q| wmax(P)^3 to a point, with one bit of headroom.  The flush
 // converts each exact sum to FP64; that value goes to the caller's FP64 mesh
 // when one is asked for, and, rounded to FP32, to the plan's FFT input (the
-// mixed form transforms in FP32).  The FP64 form accumulates with ds_add_f64
-// and keeps an FP64 FFT input.
+// mixed form transforms in FP32).  The FP64 form does the same in 64-bit
+// fixed point (FP64 products rounded to integers, ds_add_u64, 2^62 bound):
+// faster than ds_add_f64 and, like the mixed form, independent of the order
+// of the atomics; it keeps an FP64 FFT input.
 #include "tiles.h"
 
 namespace pppm {
@@ -50,15 +52,17 @@ __host__ __device__ constexpr double bspline_max(int P)
     return P == 2 ? 1.0 : P == 3 ? 0.7501 : P == 4 ? 0.6668 : P == 5 ? 0.5991 : P == 6 ? 0.5501 : 0.5111;
 }
 
-// Fixed-point exponent of a tile reading `visits` charges (see above).
-template <int P>
+// Fixed-point exponent of a tile reading `visits` charges (see above) for a
+// BITS-bit accumulator: the bound times 2^e stays below 2^(BITS - 2), one bit
+// of headroom.
+template <int P, int BITS>
 __device__ __forceinline__ int fixed_point_exponent(int visits, double qmax)
 {
     const double wm = bspline_max(P);
     const double bound = (double)visits * qmax * wm * wm * wm;
-    if (!(bound > 0.0)) return 30;
-    int e = (int)floor(log2(1073741824.0 / bound));  // 2^30: one bit of headroom
-    return e < -60 ? -60 : (e > 100 ? 100 : e);
+    if (!(bound > 0.0)) return BITS - 2;
+    int e = (int)floor(log2(ldexp(1.0, BITS - 2) / bound));
+    return e < -60 ? -60 : (e > 120 ? 120 : e);
 }
 
 template <typename A> struct Acc;
@@ -71,8 +75,12 @@ template <> struct Acc<int> {
         atomicAdd(p, r);
     }
 };
-template <> struct Acc<double> {
-    __device__ static void add(double* p, double v) { atomicAdd(p, v); }
+template <> struct Acc<long long> {
+    // FP64 form: 64-bit fixed point, the product rounded to nearest
+    __device__ static void add(long long* p, double v)
+    {
+        atomicAdd((unsigned long long*)p, (unsigned long long)__double2ll_rn(v));
+    }
 };
 
 template <int P, typename R, typename A>
@@ -113,7 +121,8 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
     __syncthreads();
     const int total = rt.pre[NRUNS];
     int e = 0;
-    if (sizeof(A) == 4) e = fixed_point_exponent<P>(total, a.stats[1]);
+    if (sizeof(A) == 4) e = fixed_point_exponent<P, 32>(total, a.stats[1]);
+    else e = fixed_point_exponent<P, 64>(total, a.stats[1]);
     const R scale = (R)ldexp(1.0, e);
     // valid y rows / z planes: [0, lim)
     const int lim_y = g.ntile[1] == 1 ? g.K[1] + H : ext[1];
@@ -257,7 +266,7 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
     const size_t lds = spread_lds_bytes(pl->geo, pl->rsize);
     dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
     if (pl->mixed) return dispatch_spread<float, int>(pl->p.order, grid, block, lds, pl->stream, a);
-    return dispatch_spread<double, double>(pl->p.order, grid, block, lds, pl->stream, a);
+    return dispatch_spread<double, long long>(pl->p.order, grid, block, lds, pl->stream, a);
 }
 
 }  // namespace pppm
