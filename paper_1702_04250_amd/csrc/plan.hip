@@ -112,8 +112,46 @@ pppm_status validate(const pppm_params* p, std::string& why)
 // block's LDS.
 bool use_hist_map(const pppm_plan_s* pl, int64_t nbins)
 {
-    return pl->hist && nbins <= HIST_MAX_BINS &&
-           (size_t)nbins * sizeof(int) + LDS_STATIC <= pl->lds_limit;
+    return nbins <= HIST_MAX_BINS && (size_t)nbins * sizeof(int) + LDS_STATIC <= pl->lds_limit;
+}
+
+// Sizes the bin arrays for nbins bins of `stride` entries each (grown when a
+// finer tiling needs more, never shrunk); returns "" or the failure.  Fresh
+// counters are zeroed on the plan's stream.
+std::string ensure_bin_buffers(pppm_plan_s* pl, int64_t nbins, int stride)
+{
+    const int64_t nent = nbins * stride;
+    if (nent > pl->bin_capacity) {
+        const int64_t scan_blocks = (nent + SCAN_BLOCK - 1) / SCAN_BLOCK;
+        int *c = nullptr, *o = nullptr, *sp = nullptr;
+        if (hipMalloc((void**)&c, nent * sizeof(int)) != hipSuccess ||
+            hipMalloc((void**)&o, (nent + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc((void**)&sp, 2 * scan_blocks * sizeof(int)) != hipSuccess ||
+            hipMemsetAsync(c, 0, nent * sizeof(int), pl->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int* b : {c, o, sp})
+                if (b) (void)hipFree(b);
+            return "out of device memory for the bin arrays";
+        }
+        for (int* b : {pl->count, pl->offsets, pl->scan_part})
+            if (b) (void)hipFree(b);
+        pl->count = c;
+        pl->offsets = o;
+        pl->scan_part = sp;
+        pl->bin_capacity = nent;
+    }
+    const size_t hist_bytes = stride == 1 ? (size_t)HIST_MAX_BLOCKS * nbins * sizeof(int) : 0;
+    if (hist_bytes > pl->hist_bytes) {
+        int* h = nullptr;
+        if (hipMalloc((void**)&h, hist_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return "out of device memory for the bin histogram";
+        }
+        if (pl->hist) (void)hipFree(pl->hist);
+        pl->hist = h;
+        pl->hist_bytes = hist_bytes;
+    }
+    return "";
 }
 
 // A tile edge B along an axis of K points is usable when the axis is a single
@@ -150,6 +188,8 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     if ((int64_t)g.ntiles * NCLASS > pl->max_bins) return "tile too fine for the plan's bin arrays";
     if (lds_s > lim || lds_g > lim || lds_a > lim)
         return "tile needs " + std::to_string(lds_s > lds_g ? lds_s : lds_g) + " bytes of LDS";
+    const std::string why = ensure_bin_buffers(pl, (int64_t)g.ntiles * NCLASS, g.bin_stride);
+    if (!why.empty()) return why;
     pl->geo = g;
     pl->nbins = (int64_t)g.ntiles * NCLASS;
     pl->stage = Stage::Empty;
@@ -380,20 +420,14 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     g.check_finite = (params->flags & PPPM_FLAG_CHECK_FINITE) ? 1 : 0;
     pl->ncell = (int64_t)g.K[0] * g.K[1] * g.K[2];
     pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
-    // bins sized for the finest allowed tiling (edges of 4 points)
-    const int64_t max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
-    pl->max_bins = max_bins;
-    const int64_t max_sub = max_bins * NSUB;
+    // finest tiling accepted: as many bins as tiles with edges of 4 points
+    pl->max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
 
     const int64_t nmax = params->max_particles;
     const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
     const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
     const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
-    const int64_t scan_blocks = (max_sub + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    if ((st = dmalloc(pl, &pl->count, max_sub * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->offsets, (max_sub + 1) * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->scan_part, 2 * scan_blocks * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
+    if ((st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->qpart, 3 * map_blocks * sizeof(double))) != PPPM_OK ||
@@ -404,13 +438,10 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->G, pl->nspec * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->epart, 2048 * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->hist, (size_t)HIST_MAX_BLOCKS * (max_bins < HIST_MAX_BINS ? max_bins : HIST_MAX_BINS) *
-                                         sizeof(int))) != PPPM_OK)
+        (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
 
-    e = hipMemsetAsync(pl->count, 0, max_sub * sizeof(int), pl->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
+    e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 8 * sizeof(double), pl->stream);
     if (e != hipSuccess) {
         pl->last_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);

@@ -68,15 +68,17 @@ struct pppm_plan_s {
     int64_t ncell = 0;   // Kx Ky Kz
     int64_t nspec = 0;   // Kz Ky (Kx/2 + 1): half spectrum of a real transform
     int64_t nbins = 0;   // tiles x NCLASS
-    int64_t max_bins = 0;  // bins the count / offset arrays hold (each NSUB sub-bins)
+    int64_t max_bins = 0;      // most bins a tiling may have (tiles of edge 4)
+    int64_t bin_capacity = 0;  // entries the count / offset arrays hold
+    size_t hist_bytes = 0;     // bytes of the per-block histogram buffer
     int ncomp = 1;       // field meshes of the forward gather: 3 (ik) or 1 (ad)
     bool mixed = true;
     size_t rsize = 4;    // bytes of the particle-side real type (float / double)
 
     // device buffers owned by the plan
-    int* count = nullptr;      // [nbins * NSUB] charges per sub-bin (kept zero between calls)
-    int* offsets = nullptr;    // [nbins * NSUB + 1] exclusive prefix of count
-    int* scan_part = nullptr;  // [2 * ceil(nbins * NSUB / SCAN_BLOCK)] chunk sums, then chunk maxima of count
+    int* count = nullptr;      // [nbins * bin_stride] charges per (sub-)bin (kept zero between calls)
+    int* offsets = nullptr;    // [nbins * bin_stride + 1] exclusive prefix of count
+    int* scan_part = nullptr;  // [2 * ceil(nbins * bin_stride / SCAN_BLOCK)] chunk sums, then chunk maxima
     int* slot = nullptr;       // [max_particles] rank of a particle within its sub-bin
     void* records = nullptr;   // [max_particles] float4 / double4 (t_x, t_y, t_z, q) in binned order;
                                // t = stencil start within the tile + fraction
@@ -93,7 +95,7 @@ struct pppm_plan_s {
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;
     int64_t qpart_blocks = 0;
-    int* hist = nullptr;       // [HIST_MAX_BLOCKS * min(max_bins, HIST_MAX_BINS)] per-block bin counts,
+    int* hist = nullptr;       // [HIST_MAX_BLOCKS * nbins] (histogram form) per-block bin counts,
                                // then per-block offsets within each bin
     int hist_blocks = 0;       // blocks of the last histogram map
     int hist_chunk = 0;        // charges per block of the last histogram map

@@ -291,3 +291,20 @@ def test_interfacial_slab(diff):
     w = W.interfacial()
     run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed", torch.float32,
                   label="interfacial")
+
+
+@pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
+def test_mesh_charge_independent_of_particle_order(prec, io):
+    # make_rho sums in exact fixed point: any order of the charges (and of the
+    # LDS atomics) gives the same bits
+    w = W.config(2)
+    dev = torch.device("cuda:0")
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", prec, io, w.n)
+    pos = torch.tensor(w.pos, dtype=io, device=dev)
+    q = torch.tensor(w.q, dtype=io, device=dev)
+    perm = torch.tensor(np.random.default_rng(11).permutation(w.n), device=dev)
+    r1 = plan.compute(pos, q, want_rho=True)["rho"].clone()
+    r2 = plan.compute(pos[perm].contiguous(), q[perm].contiguous(), want_rho=True)["rho"]
+    plan.sync()
+    assert torch.equal(r1, r2)
+    plan.close()
