@@ -434,6 +434,20 @@ def main():
                               "make_rho_fieldforce_particles_per_s":
                                   wi.n / ((ri["make_rho_us"] + ri["fieldforce_us"]) * 1e-6)}
         plan_i.close()
+        # tabulated stencil weights (the paper's table variant): speed, and the
+        # force difference from the polynomial weights
+        tab = {}
+        f_poly = f_ad.double()
+        for T in (500, 5000):
+            plan_t = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                              max_particles=n, device=dev, stream=stream, weight_table=T)
+            rt, f_t, _ = run_loop(torch, plan_t, pos, q, min(args.steps, 20), args.warmup, "ad")
+            plan_t.sync()
+            d = f_t.double() - f_poly
+            tab[str(T)] = {"make_rho_us": rt["make_rho_us"], "fieldforce_us": rt["fieldforce_us"],
+                           "forces_rms_rel_vs_polynomial": float(torch.sqrt((d * d).sum() / (f_poly * f_poly).sum()))}
+            plan_t.close()
+        out["weight_table"] = tab
         # the largest system: 4,194,304 charges of water, 256^3, P = 7
         w5 = workloads.config(5)
         pos5 = torch.tensor(w5.pos, dtype=torch.float32, device=dev).contiguous()

@@ -93,6 +93,13 @@ typedef enum { PPPM_PREC_FP64 = 0, PPPM_PREC_MIXED = 1 } pppm_prec;
 typedef enum { PPPM_F32 = 0, PPPM_F64 = 1 } pppm_dtype;
 
 #define PPPM_FLAG_CHECK_FINITE 1u
+/* Stencil weights from a table instead of their polynomials: the variant the
+ * paper describes for its mapping functions (Section 3.1), T + 1 entries per
+ * weight at the fractions i / T, the nearest entry used.  An approximation
+ * whose error falls as 1 / T.  T is given in flag bits 8..23 by
+ * PPPM_WEIGHT_TABLE_SIZE(T), 16 <= T <= 65535; 0 there means T = 5000. */
+#define PPPM_FLAG_WEIGHT_TABLE 2u
+#define PPPM_WEIGHT_TABLE_SIZE(T) (((uint32_t)(T) & 0xFFFFu) << 8)
 
 typedef struct {
     double box_lo[3];      /* lower corner of the periodic box */

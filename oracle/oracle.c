@@ -94,6 +94,18 @@ void oracle_weights(int P, double f, double *w, double *dw)
     }
 }
 
+/*
+ * Weights of one particle's stencil.  table = 0: at its fraction f.  table =
+ * T > 0: the tabulated variant of the mapping functions (Section 3.1), the
+ * weights read from a table of their values at f = i / T, i = 0..T, nearest
+ * entry; that is the weights at f rounded to the nearest multiple of 1 / T.
+ */
+static void stencil_at(int P, double f, int table, double *w, double *dw)
+{
+    if (table > 0) f = floor(f * (double)table + 0.5) / (double)table;
+    oracle_weights(P, f, w, dw);
+}
+
 /* Per-particle stencil start (unwrapped) and fraction for all three axes. */
 void oracle_particle_map(int64_t n, const double *pos, const double *lo,
                          const double *len, const int32_t *K, int P,
@@ -110,7 +122,7 @@ void oracle_particle_map(int64_t n, const double *pos, const double *lo,
 /* Map-Charge: rho_m = sum_i q_i wx wy wz over each particle's P^3 stencil. */
 void oracle_make_rho(int64_t n, const double *pos, const double *q,
                      const double *lo, const double *len, const int32_t *K,
-                     int P, double *rho)
+                     int P, int table, double *rho)
 {
     const long Kx = K[0], Ky = K[1], Kz = K[2];
     memset(rho, 0, sizeof(double) * (size_t)(Kx * Ky * Kz));
@@ -119,7 +131,7 @@ void oracle_make_rho(int64_t n, const double *pos, const double *q,
         double f[3], w[3][ORACLE_MAX_ORDER];
         for (int d = 0; d < 3; ++d) {
             map_axis(pos[3 * i + d], lo[d], len[d], K[d], P, &s[d], &f[d]);
-            oracle_weights(P, f[d], w[d], NULL);
+            stencil_at(P, f[d], table, w[d], NULL);
         }
         for (int jz = 0; jz < P; ++jz)
             for (int jy = 0; jy < P; ++jy)
@@ -138,7 +150,7 @@ void oracle_make_rho(int64_t n, const double *pos, const double *q,
  */
 void oracle_fieldforce_ik(int64_t n, const double *pos, const double *q,
                           const double *lo, const double *len, const int32_t *K,
-                          int P, const double *ex, const double *ey,
+                          int P, int table, const double *ex, const double *ey,
                           const double *ez, double *force)
 {
     const long Kx = K[0], Ky = K[1];
@@ -147,7 +159,7 @@ void oracle_fieldforce_ik(int64_t n, const double *pos, const double *q,
         double f[3], w[3][ORACLE_MAX_ORDER];
         for (int d = 0; d < 3; ++d) {
             map_axis(pos[3 * i + d], lo[d], len[d], K[d], P, &s[d], &f[d]);
-            oracle_weights(P, f[d], w[d], NULL);
+            stencil_at(P, f[d], table, w[d], NULL);
         }
         double acc[3] = {0.0, 0.0, 0.0};
         for (int jz = 0; jz < P; ++jz)
@@ -176,7 +188,7 @@ void oracle_fieldforce_ik(int64_t n, const double *pos, const double *q,
  */
 void oracle_fieldforce_ad(int64_t n, const double *pos, const double *q,
                           const double *lo, const double *len, const int32_t *K,
-                          int P, const double *phi, double *force, double *pot)
+                          int P, int table, const double *phi, double *force, double *pot)
 {
     const long Kx = K[0], Ky = K[1];
     for (int64_t i = 0; i < n; ++i) {
@@ -184,7 +196,7 @@ void oracle_fieldforce_ad(int64_t n, const double *pos, const double *q,
         double f[3], w[3][ORACLE_MAX_ORDER], dw[3][ORACLE_MAX_ORDER];
         for (int d = 0; d < 3; ++d) {
             map_axis(pos[3 * i + d], lo[d], len[d], K[d], P, &s[d], &f[d]);
-            oracle_weights(P, f[d], w[d], dw[d]);
+            stencil_at(P, f[d], table, w[d], dw[d]);
         }
         double gx = 0.0, gy = 0.0, gz = 0.0, p = 0.0;
         for (int jz = 0; jz < P; ++jz)

@@ -61,10 +61,10 @@ def _load():
         lp = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_weights.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         lib.oracle_particle_map.argtypes = [ctypes.c_int64, dp, dp, dp, ip, ctypes.c_int, lp, dp]
-        lib.oracle_make_rho.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int, dp]
-        lib.oracle_fieldforce_ik.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int,
+        lib.oracle_make_rho.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int, dp]
+        lib.oracle_fieldforce_ik.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int,
                                              dp, dp, dp, dp]
-        lib.oracle_fieldforce_ad.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int,
+        lib.oracle_fieldforce_ad.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int,
                                              dp, dp, dp]
         lib.oracle_influence_function.argtypes = [dp, ip, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                                   ctypes.c_int, dp]
@@ -81,9 +81,13 @@ def _f64(a):
 
 
 class Box:
-    """Orthorhombic periodic box with an FFT mesh and a stencil order."""
+    """Orthorhombic periodic box with an FFT mesh and a stencil order.
 
-    def __init__(self, box_lo, box_len, mesh, order):
+    table = 0: stencil weights from their polynomials; T > 0: the tabulated
+    variant of the mapping functions (Section 3.1), weights read from a table
+    of their values at fractions i / T (nearest entry)."""
+
+    def __init__(self, box_lo, box_len, mesh, order, table=0):
         self.lo = _f64(box_lo).reshape(3)
         self.len = _f64(box_len).reshape(3)
         self.mesh = np.ascontiguousarray(mesh, dtype=np.int32).reshape(3)
@@ -92,6 +96,7 @@ class Box:
             raise ValueError("order must be in [2, 7]")
         self.h = self.len / self.mesh
         self.volume = float(np.prod(self.len))
+        self.table = int(table)
 
     @property
     def shape(self):
@@ -133,7 +138,7 @@ def make_rho(pos, q, box: Box):
     q = _f64(q).reshape(-1)
     rho = np.zeros(box.shape)
     lib.oracle_make_rho(pos.shape[0], _dp(pos), _dp(q), _dp(box.lo), _dp(box.len),
-                        box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order, _dp(rho))
+                        box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order, box.table, _dp(rho))
     return rho
 
 
@@ -144,7 +149,7 @@ def fieldforce_ik(pos, q, box: Box, ex, ey, ez):
     ex, ey, ez = _f64(ex), _f64(ey), _f64(ez)
     force = np.zeros((pos.shape[0], 3))
     lib.oracle_fieldforce_ik(pos.shape[0], _dp(pos), _dp(q), _dp(box.lo), _dp(box.len),
-                             box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order,
+                             box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order, box.table,
                              _dp(ex), _dp(ey), _dp(ez), _dp(force))
     return force
 
@@ -158,7 +163,7 @@ def fieldforce_ad(pos, q, box: Box, phi):
     force = np.zeros((pos.shape[0], 3))
     pot = np.zeros(pos.shape[0])
     lib.oracle_fieldforce_ad(pos.shape[0], _dp(pos), _dp(q), _dp(box.lo), _dp(box.len),
-                             box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order,
+                             box.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), box.order, box.table,
                              _dp(phi), _dp(force), _dp(pot))
     return force, pot
 
@@ -261,13 +266,13 @@ def background_energy(q, g_ewald, coulomb_c, volume):
 
 
 def pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad",
-         want_phi=False, G=None):
+         want_phi=False, G=None, table=0):
     """One full PPPM long-range evaluation in FP64.
 
     Returns dict: rho, G, e_mesh, e_self, e_bg, energy, forces, and phi/pot
     (ad, or when want_phi), ex/ey/ez (ik).
     """
-    box = Box(box_lo, box_len, mesh, order)
+    box = Box(box_lo, box_len, mesh, order, table)
     pos = _f64(pos).reshape(-1, 3)
     q = _f64(q).reshape(-1)
     if G is None:
@@ -292,7 +297,7 @@ def pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad"
     return res
 
 
-def energy_gradients(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", G=None):
+def energy_gradients(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", G=None, table=0):
     """Adjoint of E = E_mesh + E_self + E_bg with respect to positions and charges.
 
     E_mesh = 1/2 rho^T A rho with A symmetric, so
@@ -301,7 +306,7 @@ def energy_gradients(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.
     where phi is the mesh potential of the same influence function that
     defines E (that of the plan's differentiation mode).
     """
-    res = pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c, diff, want_phi=True, G=G)
+    res = pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c, diff, want_phi=True, G=G, table=table)
     box = res["box"]
     q = _f64(q).reshape(-1)
     f_ad, pot = fieldforce_ad(pos, q, box, res["phi"])

@@ -27,6 +27,7 @@ DIFF = {"ik": 0, "ad": 1}
 PREC = {"fp64": 0, "mixed": 1}
 IO_DTYPE = {torch.float32: 0, torch.float64: 1}
 FLAG_CHECK_FINITE = 1
+FLAG_WEIGHT_TABLE = 2
 
 
 class PPPMError(RuntimeError):
@@ -99,7 +100,9 @@ def load():
 
 
 def make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", prec="mixed",
-                io_dtype=torch.float32, max_particles=0, check_finite=False) -> Params:
+                io_dtype=torch.float32, max_particles=0, check_finite=False, weight_table=0) -> Params:
+    """weight_table: 0 = polynomial stencil weights; T > 0 = a table of T + 1
+    entries per weight (PPPM_FLAG_WEIGHT_TABLE with PPPM_WEIGHT_TABLE_SIZE(T))."""
     p = Params()
     p.box_lo[:] = [float(v) for v in box_lo]
     p.box_len[:] = [float(v) for v in box_len]
@@ -112,6 +115,8 @@ def make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad",
     p.io_dtype = IO_DTYPE[io_dtype] if isinstance(io_dtype, torch.dtype) else int(io_dtype)
     p.max_particles = int(max_particles)
     p.flags = FLAG_CHECK_FINITE if check_finite else 0
+    if weight_table:
+        p.flags |= FLAG_WEIGHT_TABLE | ((int(weight_table) & 0xFFFF) << 8)
     return p
 
 
@@ -132,7 +137,8 @@ class Plan:
     """A PPPM plan on one device and stream (see include/pppm.h)."""
 
     def __init__(self, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", prec="mixed",
-                 io_dtype=torch.float32, max_particles=1, check_finite=False, device=None, stream=None):
+                 io_dtype=torch.float32, max_particles=1, check_finite=False, device=None, stream=None,
+                 weight_table=0):
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the PPPM library runs only on an MI355X")
@@ -146,7 +152,7 @@ class Plan:
         self.mesh = tuple(int(k) for k in mesh)
         self.max_particles = int(max_particles)
         self.params = make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c, diff, prec, io_dtype,
-                                  max_particles, check_finite)
+                                  max_particles, check_finite, weight_table)
         self.generation = 0
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

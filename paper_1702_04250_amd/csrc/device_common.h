@@ -130,6 +130,27 @@ __device__ __forceinline__ void bspline(R f, R (&w)[P], R (&dw)[P])
     }
 }
 
+// Stencil weights of one axis from the polynomials or, when the plan carries
+// a table (the tabulated variant of the mapping functions, paper Section
+// 3.1), from its nearest entry: T + 1 rows at f = i / T, each the P weights
+// followed by the P derivative weights.
+template <int P, typename R, bool DERIV, bool TAB>
+__device__ __forceinline__ void stencil_weights(R f, const MapGeo& g, R (&w)[P], R (&dw)[P])
+{
+    if constexpr (TAB) {
+        int i = (int)(f * (R)g.wtab_n + R(0.5));
+        i = i < 0 ? 0 : (i > g.wtab_n ? g.wtab_n : i);
+        const R* row = (const R*)g.wtab + (size_t)i * (2 * P);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            w[j] = row[j];
+            if (DERIV) dw[j] = row[P + j];
+        }
+    } else {
+        bspline<P, R, DERIV>(f, w, dw);
+    }
+}
+
 // Inclusive warp-level scan over a 64-wide wavefront.
 __device__ __forceinline__ int wave_inclusive_scan(int v)
 {

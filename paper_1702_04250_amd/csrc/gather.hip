@@ -46,7 +46,7 @@ template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
 template <> struct Vec16<double> { using T = double2; };
 
-template <int P, int MODE, typename R, typename TO>
+template <int P, int MODE, typename R, typename TO, bool TAB>
 __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
 {
     constexpr int NC = (MODE == GATHER_IK) ? 3 : 1;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                 for (int d = 0; d < 3; ++d) {
                     R f;
                     decode_local<R>(tt[d], ext[d], l[d], f);  // own charge: start in [0, ext)
-                    bspline<P, R, DERIV>(f, w[d], dw[d]);
+                    stencil_weights<P, R, DERIV, TAB>(f, g, w[d], dw[d]);
                 }
             }
             const R* base = fld + l[2] * plane + l[1] * a.pitch_x + l[0];
@@ -287,19 +287,26 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     }
 }
 
-template <int MODE, typename R, typename TO>
+template <int MODE, typename R, typename TO, bool TAB>
 hipError_t dispatch_gather(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const GatherArgs& a)
 {
     switch (P) {
-    case 2: k_gather<2, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
-    case 3: k_gather<3, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
-    case 4: k_gather<4, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
-    case 5: k_gather<5, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
-    case 6: k_gather<6, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
-    case 7: k_gather<7, MODE, R, TO><<<grid, block, lds, st>>>(a); break;
+    case 2: k_gather<2, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
+    case 3: k_gather<3, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
+    case 4: k_gather<4, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
+    case 5: k_gather<5, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
+    case 6: k_gather<6, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
+    case 7: k_gather<7, MODE, R, TO, TAB><<<grid, block, lds, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int MODE, typename R, typename TO>
+hipError_t dispatch_tab(const pppm_plan_s* pl, int P, dim3 grid, dim3 block, size_t lds, const GatherArgs& a)
+{
+    return pl->geo.wtab ? dispatch_gather<MODE, R, TO, true>(P, grid, block, lds, pl->stream, a)
+                        : dispatch_gather<MODE, R, TO, false>(P, grid, block, lds, pl->stream, a);
 }
 
 template <int MODE>
@@ -308,10 +315,10 @@ hipError_t dispatch_types(const pppm_plan_s* pl, dim3 grid, dim3 block, size_t l
     const bool f32io = pl->p.io_dtype == PPPM_F32;
     const int P = pl->p.order;
     if (pl->mixed)
-        return f32io ? dispatch_gather<MODE, float, float>(P, grid, block, lds, pl->stream, a)
-                     : dispatch_gather<MODE, float, double>(P, grid, block, lds, pl->stream, a);
-    return f32io ? dispatch_gather<MODE, double, float>(P, grid, block, lds, pl->stream, a)
-                 : dispatch_gather<MODE, double, double>(P, grid, block, lds, pl->stream, a);
+        return f32io ? dispatch_tab<MODE, float, float>(pl, P, grid, block, lds, a)
+                     : dispatch_tab<MODE, float, double>(pl, P, grid, block, lds, a);
+    return f32io ? dispatch_tab<MODE, double, float>(pl, P, grid, block, lds, a)
+                 : dispatch_tab<MODE, double, double>(pl, P, grid, block, lds, a);
 }
 
 }  // namespace

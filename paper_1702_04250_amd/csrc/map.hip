@@ -363,6 +363,13 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
     const int bin = bin_of(g, s, sl);
     const int dest = hist ? offsets[bin] + hist[(size_t)(i / chunk) * nbins + bin] + slot[i]
                           : offsets[bin * NSUB + (i & (NSUB - 1))] + slot[i];
+    if (g.wtab) {
+        // tabulated weights: the nearest table node is chosen here, in FP64
+        // (the record keeps the node's fraction, from which the kernels
+        // recover the same entry in either precision)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) f[d] = floor(f[d] * (double)g.wtab_n + 0.5) / (double)g.wtab_n;
+    }
     typename Rec<R>::T r;
     r.x = (R)((double)sl[0] + f[0]);
     r.y = (R)((double)sl[1] + f[1]);

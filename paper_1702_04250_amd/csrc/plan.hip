@@ -10,7 +10,10 @@
 #include <mutex>
 #include <string>
 
+#include "device_common.h"
 #include "pppm_internal.h"
+
+#include <vector>
 
 using namespace pppm;
 
@@ -101,8 +104,17 @@ pppm_status validate(const pppm_params* p, std::string& why)
         why = "max_particles must be in [0, 2^31 - 1]";
         return PPPM_ERR_ARG;
     }
-    if (p->flags & ~PPPM_FLAG_CHECK_FINITE) {
+    if (p->flags & ~(PPPM_FLAG_CHECK_FINITE | PPPM_FLAG_WEIGHT_TABLE | PPPM_WEIGHT_TABLE_SIZE(0xFFFF))) {
         why = "unknown flag bits";
+        return PPPM_ERR_ARG;
+    }
+    const uint32_t tsize = (p->flags >> 8) & 0xFFFFu;
+    if (tsize != 0 && !(p->flags & PPPM_FLAG_WEIGHT_TABLE)) {
+        why = "a weight-table size needs PPPM_FLAG_WEIGHT_TABLE";
+        return PPPM_ERR_ARG;
+    }
+    if (tsize != 0 && tsize < 16) {
+        why = "weight-table size must be at least 16";
         return PPPM_ERR_ARG;
     }
     return PPPM_OK;
@@ -152,6 +164,44 @@ std::string ensure_bin_buffers(pppm_plan_s* pl, int64_t nbins, int stride)
         pl->hist_bytes = hist_bytes;
     }
     return "";
+}
+
+// Host evaluation of the stencil weights and their derivatives (the same
+// centred polynomial pieces the kernels evaluate), for the weight table.
+template <int PP>
+void host_weights(double f, double* w, double* dw)
+{
+    using Cf = WeightPoly<PP>;
+    const double g = f - 0.5, g2 = g * g;
+    for (int j = 0; j < (PP + 1) / 2; ++j) {
+        double e = 0.0, o = 0.0, de = 0.0, dq = 0.0;
+        for (int m = PP - 1; m >= 0; --m) {
+            if (m % 2 == 0) e = e * g2 + Cf::c[j][m];
+            else o = o * g2 + Cf::c[j][m];
+        }
+        for (int m = PP - 2; m >= 0; --m) {
+            if (m % 2 == 0) de = de * g2 + (m + 1) * Cf::c[j][m + 1];
+            else dq = dq * g2 + (m + 1) * Cf::c[j][m + 1];
+        }
+        w[j] = e + g * o;
+        dw[j] = de + g * dq;
+        if (PP - 1 - j != j) {
+            w[PP - 1 - j] = e - g * o;
+            dw[PP - 1 - j] = g * dq - de;
+        }
+    }
+}
+
+void host_weights(int P, double f, double* w, double* dw)
+{
+    switch (P) {
+    case 2: host_weights<2>(f, w, dw); break;
+    case 3: host_weights<3>(f, w, dw); break;
+    case 4: host_weights<4>(f, w, dw); break;
+    case 5: host_weights<5>(f, w, dw); break;
+    case 6: host_weights<6>(f, w, dw); break;
+    default: host_weights<7>(f, w, dw); break;
+    }
 }
 
 // A tile edge B along an axis of K points is usable when the axis is a single
@@ -257,6 +307,33 @@ pppm_status dmalloc(pppm_plan_s* pl, T** ptr, size_t bytes)
     return PPPM_OK;
 }
 
+// Builds the plan's weight table (PPPM_FLAG_WEIGHT_TABLE): T + 1 rows at
+// f = i / T of the P weights and the P derivative weights, in the particle-
+// side precision.
+pppm_status build_weight_table(pppm_plan_s* pl)
+{
+    const uint32_t ts = (pl->p.flags >> 8) & 0xFFFFu;
+    const int T = ts ? (int)ts : 5000;
+    const int P = pl->p.order;
+    std::vector<double> h((size_t)(T + 1) * 2 * P);
+    for (int i = 0; i <= T; ++i) host_weights(P, (double)i / T, &h[(size_t)i * 2 * P], &h[(size_t)i * 2 * P + P]);
+    std::vector<float> hf;
+    const void* src = h.data();
+    size_t bytes = h.size() * sizeof(double);
+    if (pl->mixed) {
+        hf.assign(h.begin(), h.end());
+        src = hf.data();
+        bytes = hf.size() * sizeof(float);
+    }
+    pppm_status st = dmalloc(pl, &pl->wtab, bytes);
+    if (st != PPPM_OK) return st;
+    const hipError_t e = hipMemcpy(pl->wtab, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("weight table upload: ") + hipGetErrorString(e));
+    pl->geo.wtab = pl->wtab;
+    pl->geo.wtab_n = T;
+    return PPPM_OK;
+}
+
 void release(pppm_plan_s* pl)
 {
     if (pl->fft_fwd) rocfft_plan_destroy(pl->fft_fwd);
@@ -264,7 +341,7 @@ void release(pppm_plan_s* pl)
     if (pl->fft_inv1) rocfft_plan_destroy(pl->fft_inv1);
     if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
     void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart, pl->hist,
-                    pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags,
+                    pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags, pl->wtab,
                     pl->fft_work};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -453,6 +530,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         return bail(PPPM_ERR_HIP);
     }
     if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
+    if ((params->flags & PPPM_FLAG_WEIGHT_TABLE) && (st = build_weight_table(pl)) != PPPM_OK) return bail(st);
 
     pl->spread_cfg.threads = 1024;
     pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;

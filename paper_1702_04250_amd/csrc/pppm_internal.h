@@ -48,6 +48,8 @@ struct MapGeo {
     int halo;         // P - 1
     int check_finite;
     int bin_stride;   // offsets entries per bin: 1 (histogram map) or NSUB (atomic map)
+    const void* wtab; // stencil-weight table of type R ([wtab_n + 1][2P]) or null: polynomials
+    int wtab_n;       // table intervals T
 };
 
 struct LaunchCfg {
@@ -91,6 +93,7 @@ struct pppm_plan_s {
     double* G = nullptr;       // [nspec] (C / V) G(k)
     double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
     double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, max count, max |q|
+    void* wtab = nullptr;      // stencil-weight table (PPPM_FLAG_WEIGHT_TABLE)
     int* flags = nullptr;      // [1] sticky non-finite flag
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;

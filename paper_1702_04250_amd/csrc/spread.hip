@@ -83,7 +83,7 @@ template <> struct Acc<long long> {
     }
 };
 
-template <int P, typename R, typename A>
+template <int P, typename R, typename A, bool TAB>
 __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
             int s;
             R f;
             decode_local<R>(tt[d], (exp_ >> (8 * d)) & 255, s, f);
-            bspline<P, R, false>(f, w[d], unused);
+            stencil_weights<P, R, false, TAB>(f, g, w[d], unused);
             // tile coordinate of the stencil start: negative for a charge of
             // the lower neighbour
             dd[d] = s + ((shp >> (8 * d)) & 255) - 128;
@@ -225,16 +225,16 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
     }
 }
 
-template <typename R, typename A>
+template <typename R, typename A, bool TAB>
 hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
 {
     switch (P) {
-    case 2: k_spread<2, R, A><<<grid, block, lds, st>>>(a); break;
-    case 3: k_spread<3, R, A><<<grid, block, lds, st>>>(a); break;
-    case 4: k_spread<4, R, A><<<grid, block, lds, st>>>(a); break;
-    case 5: k_spread<5, R, A><<<grid, block, lds, st>>>(a); break;
-    case 6: k_spread<6, R, A><<<grid, block, lds, st>>>(a); break;
-    case 7: k_spread<7, R, A><<<grid, block, lds, st>>>(a); break;
+    case 2: k_spread<2, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 3: k_spread<3, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 4: k_spread<4, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 5: k_spread<5, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 6: k_spread<6, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 7: k_spread<7, R, A, TAB><<<grid, block, lds, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -265,8 +265,12 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
     a.stats = pl->eterms + 6;
     const size_t lds = spread_lds_bytes(pl->geo, pl->rsize);
     dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
-    if (pl->mixed) return dispatch_spread<float, int>(pl->p.order, grid, block, lds, pl->stream, a);
-    return dispatch_spread<double, long long>(pl->p.order, grid, block, lds, pl->stream, a);
+    const bool tab = pl->geo.wtab != nullptr;
+    if (pl->mixed)
+        return tab ? dispatch_spread<float, int, true>(pl->p.order, grid, block, lds, pl->stream, a)
+                   : dispatch_spread<float, int, false>(pl->p.order, grid, block, lds, pl->stream, a);
+    return tab ? dispatch_spread<double, long long, true>(pl->p.order, grid, block, lds, pl->stream, a)
+               : dispatch_spread<double, long long, false>(pl->p.order, grid, block, lds, pl->stream, a);
 }
 
 }  // namespace pppm

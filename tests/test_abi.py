@@ -87,3 +87,23 @@ def test_binding_refuses_cpu_tensors_without_gpu(lib):
         pytest.skip("has a GPU")
     with pytest.raises(RuntimeError):
         pkg.Plan((0, 0, 0), (10, 10, 10), (8, 8, 8), 5, 0.3, max_particles=10)
+
+
+@pytest.mark.parametrize("flags,code", [
+    (binding.FLAG_WEIGHT_TABLE, 0),                       # default table size
+    (binding.FLAG_WEIGHT_TABLE | (500 << 8), 0),
+    (binding.FLAG_WEIGHT_TABLE | (65535 << 8), 0),
+    (binding.FLAG_WEIGHT_TABLE | (15 << 8), -1),          # too small
+    (500 << 8, -1),                                       # size without the flag
+    (1 << 30, -1),                                        # unknown bit
+])
+def test_validate_weight_table_flags(lib, flags, code):
+    p = good()
+    p.flags = flags
+    assert binding.validate(p) == code, binding.last_error()
+
+
+def test_make_params_weight_table():
+    p = good(weight_table=500)
+    assert p.flags == binding.FLAG_WEIGHT_TABLE | (500 << 8)
+    assert good().flags == 0

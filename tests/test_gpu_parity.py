@@ -8,6 +8,7 @@ import torch
 
 import workloads as W
 from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, rho_err, rms_rel
+from oracle import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -308,3 +309,21 @@ def test_mesh_charge_independent_of_particle_order(prec, io):
     plan.sync()
     assert torch.equal(r1, r2)
     plan.close()
+
+
+@pytest.mark.parametrize("T", [500, 5000])
+@pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_weight_table_variant(T, prec, io, diff):
+    # the tabulated stencil weights against the oracle's tabulated variant
+    w = W.config(2)
+    pos_r, q_r = io_round(w.pos, w.q, io)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, w.n,
+                     weight_table=T)
+    print(f"case weight table T={T} {diff} {prec} io={io}", flush=True)
+    gpu = gpu_run(plan, pos_r, q_r, io)
+    plan.close()
+    ref = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, table=T)
+    errs, bad = compare(gpu, ref, prec)
+    print(f"  errors {errs}", flush=True)
+    assert not bad, bad
