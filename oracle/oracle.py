@@ -18,7 +18,9 @@ NumPy.  The
 test-only Ewald sums give the exact result the mesh method approximates.
 
 Readings where the paper is silent (the influence function, the Nyquist
-derivative, the energy, the mesh-charge units) are stated at each function.
+derivative, the energy, the mesh-charge units, the ad self-force) are stated at
+each function.  The optional ad self-force correction is pinned against the
+exact force on a lone charge, which is all self-force.
 """
 from __future__ import annotations
 
@@ -208,6 +210,59 @@ def influence_function(box: Box, g_ewald: float, diff: str):
     return G
 
 
+def ad_self_force_coefficients(box: Box, G):
+    """Leading harmonics of the ad self-force (Section 2.1's ad gradient of
+    the mesh energy, applied to a charge's own mesh charge).
+
+    A lone charge q at mesh coordinate u has, with the B-spline transform
+    U(k) = prod_d sinc(k_d h_d / 2)^P and aliases k_a = k + 2 pi a / h,
+      rho_hat(k) = q sum_a U(k_a) exp(-i 2 pi a.u) exp(-i k.u h),
+    so E_mesh(u) = (C q^2 / 2V) sum_k G sum_{a,b} U(k_a) U(k_b) cos(2 pi (a-b).u).
+    The terms a - b = +-e_d and +-2 e_d give
+      E(u) = const + (C q^2 / V) sum_d [S1_d cos(2 pi u_d) + S2_d cos(4 pi u_d)] + ...,
+      S1_d = sum_k G(k) prod_{d' != d} [sum_a U_d'(a)^2] sum_a U_d(a) U_d(a + 1),
+      S2_d likewise with U_d(a) U_d(a + 2), aliases |a_d'| <= 2.
+    Returns (S1[3], S2[3]); the mixed differences (a - b along two axes) and
+    higher harmonics are left out.
+    """
+    ks = wave_numbers(box)
+    P = box.order
+    A = ALIAS_RANGE
+    ua = []  # per axis: U_d(a, n) for a = -A..A
+    for d in range(3):
+        h = box.h[d]
+        rows = []
+        for a in range(-A, A + 1):
+            x = 0.5 * (ks[d] + 2.0 * math.pi * a / h) * h
+            s = np.where(x == 0.0, 1.0, np.sin(x) / np.where(x == 0.0, 1.0, x))
+            rows.append(s ** P)
+        ua.append(np.array(rows))
+    sq = [np.sum(u * u, axis=0) for u in ua]
+    s1, s2 = np.zeros(3), np.zeros(3)
+    for d in range(3):
+        b1 = np.sum(ua[d][:-1] * ua[d][1:], axis=0)
+        b2 = np.sum(ua[d][:-2] * ua[d][2:], axis=0)
+        for b, out in ((b1, s1), (b2, s2)):
+            f = [sq[0], sq[1], sq[2]]
+            f[d] = b
+            fz, fy, fx = np.meshgrid(f[2], f[1], f[0], indexing="ij")
+            out[d] = float(np.sum(G * fz * fy * fx))
+    return s1, s2
+
+
+def ad_self_force(pos, q, box: Box, coef, coulomb_c: float):
+    """The self-force of each charge from its own mesh charge, to the leading
+    harmonics of ad_self_force_coefficients:
+      F_d = (C q^2 / (V h_d)) [2 pi S1_d sin(2 pi u_d) + 4 pi S2_d sin(4 pi u_d)],
+    u_d = (x_d - lo_d) / h_d."""
+    pos = _f64(pos).reshape(-1, 3)
+    q = _f64(q).reshape(-1)
+    s1, s2 = coef
+    u = (pos - box.lo) / box.h
+    pref = coulomb_c * (q * q)[:, None] / (box.volume * box.h[None, :])
+    return pref * (2 * math.pi * s1 * np.sin(2 * math.pi * u) + 4 * math.pi * s2 * np.sin(4 * math.pi * u))
+
+
 def derivative_wave_numbers(box: Box):
     """Per-axis derivative wavenumber for ik: k, except 0 at n = -K/2.
 
@@ -266,11 +321,14 @@ def background_energy(q, g_ewald, coulomb_c, volume):
 
 
 def pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad",
-         want_phi=False, G=None, table=0):
+         want_phi=False, G=None, table=0, self_force=False):
     """One full PPPM long-range evaluation in FP64.
 
     Returns dict: rho, G, e_mesh, e_self, e_bg, energy, forces, and phi/pot
-    (ad, or when want_phi), ex/ey/ez (ik).
+    (ad, or when want_phi), ex/ey/ez (ik).  table: tabulated stencil weights
+    (Box).  self_force (ad): forces minus each charge's self-force to its
+    leading harmonics (ad_self_force), the uncorrected ones kept as
+    forces_uncorrected; energy and potential are unchanged.
     """
     box = Box(box_lo, box_len, mesh, order, table)
     pos = _f64(pos).reshape(-1, 3)
@@ -292,6 +350,10 @@ def pppm(pos, q, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad"
         res["pot"] = pot
         if diff == "ad":
             res["forces"] = f_ad
+            if self_force:
+                res["forces_uncorrected"] = f_ad
+                res["self_force"] = ad_self_force(pos, q, box, ad_self_force_coefficients(box, G), coulomb_c)
+                res["forces"] = f_ad - res["self_force"]
         else:
             res["forces_ad_phi"] = f_ad
     return res
