@@ -448,6 +448,16 @@ def main():
                            "forces_rms_rel_vs_polynomial": float(torch.sqrt((d * d).sum() / (f_poly * f_poly).sum()))}
             plan_t.close()
         out["weight_table"] = tab
+        # ad self-force correction: the cost of its gather epilogue and the
+        # size of the correction
+        plan_s = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                          max_particles=n, device=dev, stream=stream, self_force=True)
+        rs, f_s, _ = run_loop(torch, plan_s, pos, q, min(args.steps, 20), args.warmup, "ad")
+        plan_s.sync()
+        d = f_s.double() - f_poly
+        out["ad_self_force"] = {"fieldforce_us": rs["fieldforce_us"],
+                                "correction_rms_rel": float(torch.sqrt((d * d).sum() / (f_poly * f_poly).sum()))}
+        plan_s.close()
         # the largest system: 4,194,304 charges of water, 256^3, P = 7
         w5 = workloads.config(5)
         pos5 = torch.tensor(w5.pos, dtype=torch.float32, device=dev).contiguous()

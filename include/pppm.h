@@ -100,6 +100,18 @@ typedef enum { PPPM_F32 = 0, PPPM_F64 = 1 } pppm_dtype;
  * PPPM_WEIGHT_TABLE_SIZE(T), 16 <= T <= 65535; 0 there means T = 5000. */
 #define PPPM_FLAG_WEIGHT_TABLE 2u
 #define PPPM_WEIGHT_TABLE_SIZE(T) (((uint32_t)(T) & 0xFFFFu) << 8)
+/* ad only (PPPM_ERR_ARG with ik): subtract from each ad force the charge's
+ * self-force, the force its own mesh charge exerts on it.  With ad the
+ * gradient of the interpolated potential is not symmetric between a charge
+ * and its own stencil (Section 2.1's ad mode), so a lone charge feels a force
+ * that is periodic in its position within a mesh cell.  It is removed to its
+ * leading harmonics, per axis
+ *   F_self,d = q^2 / h_d [2 pi S1_d sin(2 pi u_d) + 4 pi S2_d sin(4 pi u_d)],
+ * u = (x - lo) / h, S1_d / S2_d the sums over the spectrum of (C/V) G times
+ * the B-spline transform products of aliases one and two apart along d
+ * (computed once at plan creation).  The forces are then no longer the exact
+ * gradient of the energy; the energy and pppm_energy_backward are unchanged. */
+#define PPPM_FLAG_AD_SELF_FORCE 4u
 
 typedef struct {
     double box_lo[3];      /* lower corner of the periodic box */

@@ -28,6 +28,7 @@ PREC = {"fp64": 0, "mixed": 1}
 IO_DTYPE = {torch.float32: 0, torch.float64: 1}
 FLAG_CHECK_FINITE = 1
 FLAG_WEIGHT_TABLE = 2
+FLAG_AD_SELF_FORCE = 4
 
 
 class PPPMError(RuntimeError):
@@ -100,9 +101,11 @@ def load():
 
 
 def make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", prec="mixed",
-                io_dtype=torch.float32, max_particles=0, check_finite=False, weight_table=0) -> Params:
+                io_dtype=torch.float32, max_particles=0, check_finite=False, weight_table=0,
+                self_force=False) -> Params:
     """weight_table: 0 = polynomial stencil weights; T > 0 = a table of T + 1
-    entries per weight (PPPM_FLAG_WEIGHT_TABLE with PPPM_WEIGHT_TABLE_SIZE(T))."""
+    entries per weight (PPPM_FLAG_WEIGHT_TABLE with PPPM_WEIGHT_TABLE_SIZE(T)).
+    self_force: subtract the ad self-force (PPPM_FLAG_AD_SELF_FORCE)."""
     p = Params()
     p.box_lo[:] = [float(v) for v in box_lo]
     p.box_len[:] = [float(v) for v in box_len]
@@ -117,6 +120,8 @@ def make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad",
     p.flags = FLAG_CHECK_FINITE if check_finite else 0
     if weight_table:
         p.flags |= FLAG_WEIGHT_TABLE | ((int(weight_table) & 0xFFFF) << 8)
+    if self_force:
+        p.flags |= FLAG_AD_SELF_FORCE
     return p
 
 
@@ -138,7 +143,7 @@ class Plan:
 
     def __init__(self, box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad", prec="mixed",
                  io_dtype=torch.float32, max_particles=1, check_finite=False, device=None, stream=None,
-                 weight_table=0):
+                 weight_table=0, self_force=False):
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the PPPM library runs only on an MI355X")
@@ -152,7 +157,7 @@ class Plan:
         self.mesh = tuple(int(k) for k in mesh)
         self.max_particles = int(max_particles)
         self.params = make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c, diff, prec, io_dtype,
-                                  max_particles, check_finite, weight_table)
+                                  max_particles, check_finite, weight_table, self_force)
         self.generation = 0
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

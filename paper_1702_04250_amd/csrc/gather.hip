@@ -40,7 +40,11 @@ struct GatherArgs {
     double bg_coef;      // C pi / (V g^2)
     int vec_stage;       // tile origins and K_x allow 16-byte staging loads
     int sort_off;        // byte offset of the lane-assignment buffers in LDS
+    const double* sfc;   // ad self-force coefficients of the stencil fraction's sines, or null
 };
+
+__device__ __forceinline__ float sin_pi(float x) { return sinpif(x); }
+__device__ __forceinline__ double sin_pi(double x) { return sinpi(x); }
 
 template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
@@ -269,9 +273,24 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                 out[3 * (size_t)iu + 1] = (TO)(qv * o1);
                 out[3 * (size_t)iu + 2] = (TO)(qv * o2);
             } else if (MODE == GATHER_AD) {
-                out[3 * (size_t)iu + 0] = (TO)(-qv * o0 * (R)a.inv_h[0]);
-                out[3 * (size_t)iu + 1] = (TO)(-qv * o1 * (R)a.inv_h[1]);
-                out[3 * (size_t)iu + 2] = (TO)(-qv * o2 * (R)a.inv_h[2]);
+                R fo[3] = {-qv * o0 * (R)a.inv_h[0], -qv * o1 * (R)a.inv_h[1], -qv * o2 * (R)a.inv_h[2]};
+                if (a.sfc) {
+                    // self-force q^2 (c1_d sin(2 pi f_d) + c2_d sin(4 pi f_d)) with f_d the
+                    // stencil fraction (re-read from the record); c1 carries the sign
+                    // that turns sin(2 pi f) into sin(2 pi u) for odd orders
+                    const RT p2 = rec[sidx[k]];
+                    const R tt[3] = {p2.x, p2.y, p2.z};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        int sd;
+                        R f;
+                        decode_local<R>(tt[d], ext[d], sd, f);
+                        fo[d] -= qv * qv * ((R)a.sfc[d] * sin_pi(R(2) * f) + (R)a.sfc[3 + d] * sin_pi(R(4) * f));
+                    }
+                }
+                out[3 * (size_t)iu + 0] = (TO)fo[0];
+                out[3 * (size_t)iu + 1] = (TO)fo[1];
+                out[3 * (size_t)iu + 2] = (TO)fo[2];
             } else {
                 const double qd = (double)qv;
                 if (out) {
@@ -354,6 +373,7 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     a.out1 = out1;
     a.grad_energy = grad_energy;
     a.eterms = pl->eterms;
+    a.sfc = pl->sfc;
     a.self_coef = 2.0 * pl->p.coulomb_c * pl->p.g_ewald / sqrt(M_PI);
     const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
     a.bg_coef = pl->p.coulomb_c * M_PI / (V * pl->p.g_ewald * pl->p.g_ewald);

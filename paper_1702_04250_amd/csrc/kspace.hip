@@ -183,6 +183,84 @@ __global__ __launch_bounds__(1024) void k_energy_final(int ne, const double* __r
     }
 }
 
+// ad self-force coefficients.  A lone charge q at mesh coordinate u has the
+// mesh energy (C q^2 / 2V) sum_k G sum_{a,b} U(k_a) U(k_b) cos(2 pi (a - b).u)
+// (aliases k_a = k + 2 pi a / h, U = prod_d sinc(k_d h_d / 2)^P).  Its terms
+// with a - b = +-e_d and +-2 e_d are the position-dependent energy
+// q^2 [S1_d cos(2 pi u_d) + S2_d cos(4 pi u_d)] with
+//   S1_d = sum_k G'(k) prod_{d' != d} [sum_a U_d'(a)^2] sum_a U_d(a) U_d(a + 1),
+//   S2_d the same with U_d(a) U_d(a + 2),
+// G' = (C/V) G the plan's influence function, |a_d| <= 2, the sum over the
+// full spectrum (each half-spectrum point but the x = 0 and Nyquist planes
+// stands for two).  Its negative gradient is the self-force.  One partial
+// sum of (S1, S2) per block; the final kernel adds them in block order.
+__global__ __launch_bounds__(KSPACE_THREADS) void k_self_force_partials(KGeo kg, long long nspec, int P,
+                                                                         const double* __restrict__ G,
+                                                                         double* __restrict__ part)
+{
+    __shared__ double red[6][KSPACE_THREADS / 64];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double two_pi = 2.0 * M_PI;
+    for (long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x; idx < nspec;
+         idx += (long long)gridDim.x * KSPACE_THREADS) {
+        const int ix = (int)(idx % kg.nxh);
+        const int iy = (int)((idx / kg.nxh) % kg.K[1]);
+        const int iz = (int)(idx / ((long long)kg.nxh * kg.K[1]));
+        const int ii[3] = {ix, iy, iz};
+        double sq[3], b1[3], b2[3];
+        for (int d = 0; d < 3; ++d) {
+            const double kd = two_pi * (double)fft_index(ii[d], kg.K[d]) / kg.len[d];
+            double u[NA];
+            for (int m = 0; m < NA; ++m) {
+                const double x = 0.5 * (kd + two_pi * (double)(m - ALIAS) / kg.h[d]) * kg.h[d];
+                const double s = (x == 0.0) ? 1.0 : sin(x) / x;
+                double p = 1.0;
+                for (int e = 0; e < P; ++e) p *= s;
+                u[m] = p;
+            }
+            sq[d] = b1[d] = b2[d] = 0.0;
+            for (int m = 0; m < NA; ++m) sq[d] += u[m] * u[m];
+            for (int m = 0; m + 1 < NA; ++m) b1[d] += u[m] * u[m + 1];
+            for (int m = 0; m + 2 < NA; ++m) b2[d] += u[m] * u[m + 2];
+        }
+        const bool edge = (ix == 0) || (2 * ix == kg.K[0]);
+        const double wg = (edge ? 1.0 : 2.0) * G[idx];
+        acc[0] += wg * b1[0] * sq[1] * sq[2];
+        acc[1] += wg * sq[0] * b1[1] * sq[2];
+        acc[2] += wg * sq[0] * sq[1] * b1[2];
+        acc[3] += wg * b2[0] * sq[1] * sq[2];
+        acc[4] += wg * sq[0] * b2[1] * sq[2];
+        acc[5] += wg * sq[0] * sq[1] * b2[2];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int j = 0; j < 6; ++j) {
+        double v = acc[j];
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+        if (lane == 0) red[j][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0.0;
+        for (int w = 0; w < KSPACE_THREADS / 64; ++w) v += red[threadIdx.x][w];
+        part[6 * (size_t)blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+// Coefficients of the self-force in terms of the stencil fraction f the
+// gather holds: u = s + f + P/2 - 1 with s an integer, so sin(2 pi u) =
+// (-1)^P sin(2 pi f) and sin(4 pi u) = sin(4 pi f).
+// coef[d] = (-1)^P 2 pi S1_d / h_d, coef[3 + d] = 4 pi S2_d / h_d.
+__global__ __launch_bounds__(64) void k_self_force_final(int nblocks, KGeo kg, int P, const double* __restrict__ part,
+                                                         double* __restrict__ coef)
+{
+    const int j = threadIdx.x;
+    if (j >= 6) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[6 * (size_t)b + j];
+    const double odd = (P & 1) ? -1.0 : 1.0;
+    coef[j] = (j < 3 ? odd * 2.0 * M_PI / kg.h[j] : 4.0 * M_PI / kg.h[j - 3]) * s;
+}
+
 KGeo make_kgeo(const pppm_plan_s* pl)
 {
     KGeo kg{};
@@ -195,13 +273,23 @@ KGeo make_kgeo(const pppm_plan_s* pl)
     return kg;
 }
 
+}  // namespace
+
 int kspace_blocks(long long nspec)
 {
     const long long b = (nspec + KSPACE_THREADS - 1) / KSPACE_THREADS;
     return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
 }
 
-}  // namespace
+hipError_t launch_self_force_coef(pppm_plan_s* pl)
+{
+    const KGeo kg = make_kgeo(pl);
+    const int blocks = kspace_blocks(pl->nspec);
+    k_self_force_partials<<<blocks, KSPACE_THREADS, 0, pl->stream>>>(kg, pl->nspec, pl->p.order, pl->G,
+                                                                      pl->sfc + 6);
+    k_self_force_final<<<1, 64, 0, pl->stream>>>(blocks, kg, pl->p.order, pl->sfc + 6, pl->sfc);
+    return hipGetLastError();
+}
 
 hipError_t launch_influence(pppm_plan_s* pl)
 {

@@ -104,8 +104,13 @@ pppm_status validate(const pppm_params* p, std::string& why)
         why = "max_particles must be in [0, 2^31 - 1]";
         return PPPM_ERR_ARG;
     }
-    if (p->flags & ~(PPPM_FLAG_CHECK_FINITE | PPPM_FLAG_WEIGHT_TABLE | PPPM_WEIGHT_TABLE_SIZE(0xFFFF))) {
+    if (p->flags & ~(PPPM_FLAG_CHECK_FINITE | PPPM_FLAG_WEIGHT_TABLE | PPPM_FLAG_AD_SELF_FORCE |
+                     PPPM_WEIGHT_TABLE_SIZE(0xFFFF))) {
         why = "unknown flag bits";
+        return PPPM_ERR_ARG;
+    }
+    if ((p->flags & PPPM_FLAG_AD_SELF_FORCE) && p->diff != PPPM_DIFF_AD) {
+        why = "PPPM_FLAG_AD_SELF_FORCE needs diff = PPPM_DIFF_AD";
         return PPPM_ERR_ARG;
     }
     const uint32_t tsize = (p->flags >> 8) & 0xFFFFu;
@@ -342,7 +347,7 @@ void release(pppm_plan_s* pl)
     if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
     void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart, pl->hist,
                     pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags, pl->wtab,
-                    pl->fft_work};
+                    pl->sfc,   pl->fft_work};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -528,6 +533,15 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     if (e != hipSuccess) {
         pl->last_error = std::string("influence function: ") + hipGetErrorString(e);
         return bail(PPPM_ERR_HIP);
+    }
+    if (params->flags & PPPM_FLAG_AD_SELF_FORCE) {
+        if ((st = dmalloc(pl, &pl->sfc, (6 + 6 * (size_t)kspace_blocks(pl->nspec)) * sizeof(double))) != PPPM_OK)
+            return bail(st);
+        e = launch_self_force_coef(pl);
+        if (e != hipSuccess) {
+            pl->last_error = std::string("self-force coefficients: ") + hipGetErrorString(e);
+            return bail(PPPM_ERR_HIP);
+        }
     }
     if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
     if ((params->flags & PPPM_FLAG_WEIGHT_TABLE) && (st = build_weight_table(pl)) != PPPM_OK) return bail(st);

@@ -94,6 +94,9 @@ struct pppm_plan_s {
     double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
     double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, max count, max |q|
     void* wtab = nullptr;      // stencil-weight table (PPPM_FLAG_WEIGHT_TABLE)
+    double* sfc = nullptr;     // (PPPM_FLAG_AD_SELF_FORCE) [6 + 6 * kspace blocks]: per axis
+                               // (-1)^P 2 pi S1_d / h_d, then 4 pi S2_d / h_d (factors of the sines
+                               // of the stencil fraction); block partials after them
     int* flags = nullptr;      // [1] sticky non-finite flag
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;
@@ -131,6 +134,8 @@ hipError_t launch_scatter(pppm_plan_s* pl, int64_t n, const void* pos, const voi
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user);
 hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy);
 hipError_t launch_influence(pppm_plan_s* pl);
+hipError_t launch_self_force_coef(pppm_plan_s* pl);
+int kspace_blocks(long long nspec);
 hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only);
 hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out);
 hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);

@@ -107,3 +107,11 @@ def test_make_params_weight_table():
     p = good(weight_table=500)
     assert p.flags == binding.FLAG_WEIGHT_TABLE | (500 << 8)
     assert good().flags == 0
+
+
+@pytest.mark.parametrize("diff,code", [("ad", 0), ("ik", -1)])
+def test_validate_self_force_flag(lib, diff, code):
+    # the self-force correction is defined for ad only
+    p = good(diff=diff, self_force=True)
+    assert p.flags == binding.FLAG_AD_SELF_FORCE
+    assert binding.validate(p) == code, binding.last_error()

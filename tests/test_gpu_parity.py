@@ -327,3 +327,51 @@ def test_weight_table_variant(T, prec, io, diff):
     errs, bad = compare(gpu, ref, prec)
     print(f"  errors {errs}", flush=True)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
+def test_ad_self_force_correction(prec, io):
+    # corrected ad forces against the oracle's corrected forces, and the
+    # correction itself (corrected minus uncorrected plan) against the
+    # oracle's self-force
+    w = W.config(2)
+    pos_r, q_r = io_round(w.pos, w.q, io)
+    print(f"case ad self-force {prec} io={io}", flush=True)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ad", prec, io, w.n,
+                     self_force=True)
+    gpu = gpu_run(plan, pos_r, q_r, io)
+    plan.close()
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ad", prec, io, w.n)
+    raw = gpu_run(plan, pos_r, q_r, io)
+    plan.close()
+    ref = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ad", self_force=True)
+    errs, bad = compare(gpu, ref, prec)
+    sf_err = rms_rel(raw["forces"] - gpu["forces"], ref["self_force"])
+    print(f"  errors {errs} self-force {sf_err:.3e}", flush=True)
+    assert not bad, bad
+    assert sf_err < (1e-9 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("P", [4, 5])
+def test_ad_self_force_of_a_lone_charge(P):
+    # a lone charge's ad force is all self-force: the correction removes
+    # almost all of it (what is left are the harmonics beyond the second);
+    # even and odd orders place the stencil differently relative to the cell
+    L, K = 16.0, 16
+    rng = np.random.default_rng(11)
+    pos = rng.uniform(0, L, size=(1, 3))
+    q = np.array([1.0])
+    out = {}
+    for sf in (False, True):
+        plan = make_plan(pkg, (0, 0, 0), (L,) * 3, (K,) * 3, P, 0.6, 1.0, "ad", "fp64", torch.float64, 1,
+                         self_force=sf)
+        out[sf] = gpu_run(plan, pos, q, torch.float64)["forces"]
+        plan.close()
+    before, after = np.linalg.norm(out[False]), np.linalg.norm(out[True])
+    ref = oracle.pppm(pos, q, (0, 0, 0), (L,) * 3, (K,) * 3, P, 0.6, 1.0, "ad", self_force=True)
+    err = rms_rel(out[True], ref["forces"])
+    print(f"case lone charge P={P}: |F| {before:.3e} -> {after:.3e}, vs oracle {err:.2e}", flush=True)
+    # the residual is a small difference of FP64 values: relative to it the
+    # error is larger than relative to the uncorrected force
+    assert err < 1e-8
+    assert before > 0 and after < {4: 0.08, 5: 0.01}[P] * before

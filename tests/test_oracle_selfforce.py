@@ -22,7 +22,7 @@ def lone_charge_forces(P, K, L, g, seed=1, n=30):
     return np.array(exact), np.array(harm)
 
 
-@pytest.mark.parametrize("P,tol", [(3, 0.06), (5, 0.01), (7, 0.01)])
+@pytest.mark.parametrize("P,tol", [(3, 0.06), (4, 0.08), (5, 0.01), (7, 0.01)])
 def test_harmonics_match_the_lone_charge_force(P, tol):
     exact, harm = lone_charge_forces(P, 16, 16.0, 0.6)
     rel = np.sqrt(((exact - harm) ** 2).sum() / (exact ** 2).sum())
