@@ -167,6 +167,76 @@ def algorithmic_bytes(kind, n, cells, prec):
     raise ValueError(kind)
 
 
+FP32_VECTOR_TFLOPS = 78.6  # MI355X FP32 FMA without packed-FP32 instructions (this library is built without them)
+
+
+def algorithmic_flops(kind, P):
+    """Flops per particle, weights by Horner: weights 6P(P-1) (derivatives
+    another 6P(P-2)), spread 2P^3 + P^2 + P, ad gather 4P^3 + 9P^2, ik
+    gather 6P^3 + 7P^2."""
+    w = 6 * P * (P - 1)
+    dw = 6 * P * (P - 2)
+    if kind == "make_rho":
+        return w + 2 * P ** 3 + P * P + P
+    if kind == "fieldforce_ad":
+        return w + dw + 4 * P ** 3 + 9 * P * P
+    if kind == "fieldforce_ik":
+        return w + 6 * P ** 3 + 7 * P * P
+    raise ValueError(kind)
+
+
+def measured_copy_gbs(torch, dev, stream, nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second), the practical ceiling next to the published peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        a.fill_(1.0)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * nbytes / t / 1e9
+
+
+def order_sweep(torch, pkg, workloads, dev, stream, steps, warmup):
+    """The 524,288-charge system on its 128^3 mesh at P = 3..7 (ad, mixed):
+    make_rho and fieldforce times against both roofs (HBM bytes and FP32
+    flops), and the mixed forces against the FP64 form of the same GPU path."""
+    res = {}
+    for P in (3, 4, 5, 6, 7):
+        w = workloads.config(3, order=P)
+        pos = torch.tensor(w.pos, dtype=torch.float32, device=dev).contiguous()
+        q = torch.tensor(w.q, dtype=torch.float32, device=dev).contiguous()
+        plan = pkg.Plan(w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                        max_particles=w.n, device=dev, stream=stream)
+        r, f, _ = run_loop(torch, plan, pos, q, steps, warmup, "ad")
+        plan.sync()
+        plan.close()
+        plan = pkg.Plan(w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "fp64", torch.float64,
+                        max_particles=w.n, device=dev, stream=stream)
+        r64, f64, _ = run_loop(torch, plan, pos.double(), q.double(), 2, 1, "ad")
+        plan.sync()
+        plan.close()
+        d = f.double() - f64
+        t_rho, t_ff = r["make_rho_us"], r["fieldforce_us"]
+        b = algorithmic_bytes("make_rho", w.n, w.cells, "mixed") + algorithmic_bytes("fieldforce_ad", w.n, w.cells,
+                                                                                       "mixed")
+        fl = w.n * (algorithmic_flops("make_rho", P) + algorithmic_flops("fieldforce_ad", P))
+        t = (t_rho + t_ff) * 1e-6
+        res[str(P)] = {"make_rho_us": t_rho, "fieldforce_us": t_ff, "particles_per_s": w.n / t,
+                       "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS, "fp32_tflops": fl / t / 1e12,
+                       "alu_frac": fl / t / 1e12 / FP32_VECTOR_TFLOPS,
+                       "forces_rms_rel_vs_fp64": float(torch.sqrt((d * d).sum() / (f64 * f64).sum()))}
+        del pos, q, f, f64, d
+    return res
+
+
 class Timer:
     """Pairs of HIP events on one stream, averaged per label."""
 
@@ -458,6 +528,8 @@ def main():
         out["ad_self_force"] = {"fieldforce_us": rs["fieldforce_us"],
                                 "correction_rms_rel": float(torch.sqrt((d * d).sum() / (f_poly * f_poly).sum()))}
         plan_s.close()
+        out["order_sweep_K128"] = order_sweep(torch, pkg, workloads, dev, stream, min(args.steps, 20), args.warmup)
+        out["roofline"]["measured_copy_GBs"] = measured_copy_gbs(torch, dev, stream)
         # the largest system: 4,194,304 charges of water, 256^3, P = 7
         w5 = workloads.config(5)
         pos5 = torch.tensor(w5.pos, dtype=torch.float32, device=dev).contiguous()

@@ -1,0 +1,665 @@
+// The Poisson step (Equation 2; Section 3.2) as five passes over the mesh
+// for meshes whose three sizes are powers of two (8 .. 1024 in the mixed
+// form, 8 .. 256 in FP64); other sizes use rocFFT (plan.hip).
+//
+//   1. x, forward: each mesh row of K_x reals is packed as K_x / 2 complex
+//      values (even points real, odd points imaginary), transformed, and
+//      split into the K_x / 2 + 1 coefficients of the real transform.
+//   2. y, forward: columns along y of the half spectrum, in place.
+//   3. z: columns along z are transformed forward, multiplied by the
+//      influence function (ik: and by -i kappa_d, three outputs), the FP64
+//      energy partial sums taken, and transformed back along z.
+//   4. y, inverse, per output mesh, in place.
+//   5. x, inverse: each row's K_x / 2 + 1 coefficients are folded into
+//      K_x / 2 complex values, transformed back and unpacked into K_x reals.
+//
+// Each pass reads and writes the mesh once.  Conventions are those of the
+// library's transforms: forward sum_m rho_m exp(-i k.m h), inverse
+// unnormalised with exp(+i k.m h).  The half spectrum is stored
+// [K_z][K_y][nxp] with the K_x/2 + 1 coefficients of a row padded to a
+// 128-byte pitch, so that the column passes read whole cache lines; the
+// influence function is read from its stored octant k_y, k_z >= 0.
+//
+// Every transform of length N = N1 N2 is done in two register stages with
+// one exchange through LDS (the four-step split of the index,
+// n = t + N2 j, k = k1 + N1 k2):
+//   stage A: for each t, a length-N1 transform over j in registers, times
+//            the twiddle W_N^(t k1);
+//   stage B: for each k1, a length-N2 transform over t in registers.
+// The short transforms are unrolled radix-2 recursions whose roots are
+// compile-time constants; the twiddles W_N come from per-axis tables
+// computed in FP64 at plan creation.
+#include "device_common.h"
+
+namespace pppm {
+
+namespace {
+
+constexpr int FFT_THREADS = 256;
+
+// complex value of the spectra (same layout as float2 / double2)
+template <typename R> struct alignas(2 * sizeof(R)) Cplx {
+    R x, y;
+};
+
+template <typename R> __device__ __forceinline__ Cplx<R> cmul(Cplx<R> a, Cplx<R> b)
+{
+    return Cplx<R>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ---- compile-time roots of unity -------------------------------------------
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x)
+{
+    double t = x, s = x;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x * x / (double)((2 * n) * (2 * n + 1));
+        s += t;
+    }
+    return s;
+}
+constexpr double taylor_cos(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x * x / (double)((2 * n - 1) * (2 * n));
+        s += t;
+    }
+    return s;
+}
+// cos and sin of 2 pi k / L: the angle is reduced to its quadrant exactly
+// (integer arithmetic), then the series run on [0, pi/2).
+constexpr double root_cos(int k, int L)
+{
+    const int r = ((k % L) + L) % L;
+    const int q = (4 * r) / L;
+    const double x = 2.0 * kPi * (double)(4 * r - q * L) / (4.0 * (double)L);
+    return q == 0 ? taylor_cos(x) : q == 1 ? -taylor_sin(x) : q == 2 ? -taylor_cos(x) : taylor_sin(x);
+}
+constexpr double root_sin(int k, int L)
+{
+    const int r = ((k % L) + L) % L;
+    const int q = (4 * r) / L;
+    const double x = 2.0 * kPi * (double)(4 * r - q * L) / (4.0 * (double)L);
+    return q == 0 ? taylor_sin(x) : q == 1 ? taylor_cos(x) : q == 2 ? -taylor_sin(x) : -taylor_cos(x);
+}
+
+// v <- DFT_L(v), v[k] = sum_j v[j] exp(-+2 pi i j k / L) (INV: +), L a power
+// of two up to 32, unrolled: the halves of even and odd points, then the
+// butterflies with constant roots.
+template <int L, bool INV, typename R> struct Dft {
+    __device__ __forceinline__ static void run(Cplx<R>* v)
+    {
+        constexpr int H = L / 2;
+        Cplx<R> e[H], o[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<H, INV, R>::run(e);
+        Dft<H, INV, R>::run(o);
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const R c = (R)root_cos(k, L);
+            const R s = INV ? (R)root_sin(k, L) : (R)-root_sin(k, L);
+            Cplx<R> t;
+            if (k == 0) {
+                t = o[k];
+            } else if (4 * k == L) {  // exp(-+i pi/2)
+                t = INV ? Cplx<R>{-o[k].y, o[k].x} : Cplx<R>{o[k].y, -o[k].x};
+            } else {
+                t = Cplx<R>{c * o[k].x - s * o[k].y, c * o[k].y + s * o[k].x};
+            }
+            v[k] = Cplx<R>{e[k].x + t.x, e[k].y + t.y};
+            v[k + H] = Cplx<R>{e[k].x - t.x, e[k].y - t.y};
+        }
+    }
+};
+template <bool INV, typename R> struct Dft<1, INV, R> {
+    __device__ __forceinline__ static void run(Cplx<R>*) {}
+};
+
+// Split of N into N1 N2 (N1 >= N2, both powers of two).
+template <int N> struct Split {
+    static constexpr int lg = (N >= 1024) ? 10 : (N >= 512) ? 9 : (N >= 256) ? 8 : (N >= 128) ? 7 : (N >= 64) ? 6
+                              : (N >= 32) ? 5 : (N >= 16) ? 4 : (N >= 8) ? 3 : (N >= 4) ? 2 : 1;
+    static constexpr int N1 = 1 << ((lg + 1) / 2);
+    static constexpr int N2 = N / N1;
+};
+
+// Transforms M sequences of length N (M a power of two).  ld(n, m) gives
+// element n of sequence m, st(k, m, v) takes coefficient k; ex is an LDS
+// buffer of N * M values; tw the LDS twiddle table with W_N^i at
+// tw[i * tstride].  Every thread of the block must call it; it ends with a
+// barrier.  Tasks map m fastest so that the lanes of a wavefront touch
+// consecutive sequences.
+template <int N, bool INV, typename R, typename Ld, typename St>
+__device__ __forceinline__ void fft2(int M, Ld ld, St st, Cplx<R>* ex, const Cplx<R>* tw, int tstride)
+{
+    using C = Cplx<R>;
+    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+    const int lm = __ffs(M) - 1;
+    for (int task = threadIdx.x; task < N2 * M; task += blockDim.x) {
+        const int m = task & (M - 1), t = task >> lm;
+        C v[N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v[j] = ld(t + N2 * j, m);
+        Dft<N1, INV, R>::run(v);
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) {
+            C w = tw[t * k1 * tstride];  // t k1 < N
+            if (INV) w.y = -w.y;
+            if (t != 0) v[k1] = cmul(v[k1], w);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) ex[((k1 * N2 + t) << lm) + m] = v[k1];
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < N1 * M; task += blockDim.x) {
+        const int m = task & (M - 1), k1 = task >> lm;
+        C v[N2];
+#pragma unroll
+        for (int t = 0; t < N2; ++t) v[t] = ex[((k1 * N2 + t) << lm) + m];
+        Dft<N2, INV, R>::run(v);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) st(k1 + N1 * k2, m, v[k2]);
+    }
+    __syncthreads();
+}
+
+template <typename C> __device__ __forceinline__ void load_table(C* tw, const C* __restrict__ g, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = g[i];
+}
+
+// Element-wise copy of `total` items, dst(i) = src(i), with up to STAGE
+// loads of each thread in flight before the first store.
+constexpr int STAGE = 8;
+template <typename T, typename Ld, typename St>
+__device__ __forceinline__ void staged_copy(int total, Ld ld, St st)
+{
+    for (int i0 = threadIdx.x; i0 < total; i0 += STAGE * FFT_THREADS) {
+        T v[STAGE];
+#pragma unroll
+        for (int u = 0; u < STAGE; ++u) {
+            const int i = i0 + u * FFT_THREADS;
+            if (i < total) v[u] = ld(i);
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE; ++u) {
+            const int i = i0 + u * FFT_THREADS;
+            if (i < total) st(i, v[u]);
+        }
+    }
+}
+
+struct FftGeo {
+    int K[3];
+    int nxh;            // K_x / 2 + 1 coefficients per row
+    int nxp;            // row pitch of the spectra, nxh rounded up to 128 bytes
+    double len[3];
+    long long slot;     // elements per spectrum, K_z K_y nxp
+};
+
+// Pass 1.  `rows` rows of the real mesh per block (K_x = 2 NC points each)
+// to rows of the half spectrum.  With z_n = x_2n + i x_2n+1 and Z its
+// transform of length NC:
+//   X_k = (Z_k + conj Z_{NC-k}) / 2 + W^k (Z_k - conj Z_{NC-k}) / 2i,
+// W = exp(-2 pi i / K_x).  The rows are staged in LDS transposed, [n][m]
+// with an odd pitch rows + 1, so that both the staging and the transform
+// access LDS without bank conflicts.
+template <typename R, int NC>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_x_fwd(const R* __restrict__ in, Cplx<R>* __restrict__ out,
+                                                           int nxp, int nrows, int rows,
+                                                           const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    constexpr int Kx = 2 * NC, nxh = NC + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = rows + 1;
+    C* tw = (C*)smem_raw;
+    C* s = tw + Kx;        // [NC][P]
+    C* ex = s + NC * P;    // [NC * rows]
+    load_table(tw, twg, Kx);
+    const int r0 = blockIdx.x * rows;
+    const int nr = min(rows, nrows - r0);
+    const C* src = (const C*)(in + (size_t)r0 * Kx);
+    staged_copy<C>(
+        rows * NC, [&](int i) { return (i < nr * NC) ? src[i] : C{R(0), R(0)}; },
+        [&](int i, C v) {
+            const int m = i / NC, n = i - m * NC;
+            s[n * P + m] = v;
+        });
+    __syncthreads();
+    fft2<NC, false, R>(
+        rows, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, ex, tw, 2);
+    for (int i = threadIdx.x; i < nr * nxh; i += blockDim.x) {
+        const int m = i / nxh, k = i - m * nxh;
+        const C za = s[(k == NC ? 0 : k) * P + m];
+        const C zb = s[(k == 0 ? 0 : NC - k) * P + m];
+        const C fe = C{R(0.5) * (za.x + zb.x), R(0.5) * (za.y - zb.y)};
+        const C fo = C{R(0.5) * (za.y + zb.y), R(-0.5) * (za.x - zb.x)};
+        const C wf = cmul(tw[k], fo);
+        out[(size_t)(r0 + m) * nxp + k] = C{fe.x + wf.x, fe.y + wf.y};
+    }
+}
+
+// Passes 2 and 4.  Columns along y of one z plane, xc adjacent x per block,
+// in place (each block owns its columns); blockIdx.y selects the mesh of a
+// batch (comp_stride apart).  Loads come straight from the mesh into
+// registers and results go straight back.
+template <typename R, int KY, bool INV>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_y(Cplx<R>* __restrict__ data, int nxh, int nxp, int xc, int nchunk,
+                                                       long long comp_stride, const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* tw = (C*)smem_raw;
+    C* ex = tw + KY;
+    load_table(tw, twg, KY);
+    __syncthreads();
+    const int z = blockIdx.x / nchunk, ch = blockIdx.x - z * nchunk;
+    const int x0 = ch * xc, nx = min(xc, nxh - x0);
+    C* d = data + blockIdx.y * comp_stride + (size_t)z * KY * nxp + x0;
+    fft2<KY, INV, R>(
+        xc, [&](int n, int m) { return (m < nx) ? d[(size_t)n * nxp + m] : C{R(0), R(0)}; },
+        [&](int k, int m, C v) {
+            if (m < nx) d[(size_t)k * nxp + m] = v;
+        },
+        ex, tw, 1);
+}
+
+__device__ __forceinline__ int fft_index(int i, int K) { return (2 * i < K) ? i : i - K; }
+
+// Pass 3.  MODE 0 (ik): spec_d = z-inverse of -i kappa_d G' rho_hat, d = 0..2,
+// kappa = 0 on the Nyquist planes; MODE 1 (ad): spec_0 = z-inverse of
+// G' rho_hat; MODE 2: the potential alone into spec_0 (no energy).  Energy
+// partial per block: sum w_k G' |rho_hat|^2, w_k = 1/2 on the x = 0 and
+// x Nyquist planes (their Hermitian partners are not stored) and 1 elsewhere.
+template <typename R, int KZ, int MODE>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_solve(const Cplx<R>* __restrict__ A, Cplx<R>* __restrict__ spec,
+                                                             const double* __restrict__ G,
+                                                             double* __restrict__ epart, FftGeo fg, int xc, int nchunk,
+                                                             const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[FFT_THREADS / 64];
+    const int Ky = fg.K[1], nxh = fg.nxh;
+    const int cells = KZ * xc;
+    C* tw = (C*)smem_raw;
+    C* F = tw + KZ;    // forward transform, [n][m]
+    C* U = F + cells;  // input of an inverse transform, [n][m]
+    C* ex = U + cells;
+    load_table(tw, twg, KZ);
+    const int y = blockIdx.x / nchunk, ch = blockIdx.x - y * nchunk;
+    const int x0 = ch * xc, nx = min(xc, nxh - x0);
+    const size_t plane = (size_t)Ky * fg.nxp;
+    const C* a = A + (size_t)y * fg.nxp + x0;
+    const int lx = __ffs(xc) - 1;  // xc is a power of two
+    // G octant: rows (z, y) with z <= K_z / 2, y <= K_y / 2.  The thread's
+    // values (at most STAGE points: the host keeps cells <= STAGE *
+    // FFT_THREADS) are loaded first so that their latency overlaps the
+    // forward transform.
+    const int gny = Ky / 2 + 1;
+    const int gy = min(y, Ky - y);
+    double gk[STAGE];
+#pragma unroll
+    for (int u = 0; u < STAGE; ++u) {
+        const int i = threadIdx.x + u * FFT_THREADS;
+        const int n = i >> lx, m = i & (xc - 1);
+        gk[u] = 0.0;
+        if (i < cells && m < nx) gk[u] = G[((size_t)min(n, KZ - n) * gny + gy) * nxh + x0 + m];
+    }
+    __syncthreads();  // twiddle table
+    fft2<KZ, false, R>(
+        xc, [&](int n, int m) { return (m < nx) ? a[n * plane + m] : C{R(0), R(0)}; },
+        [&](int k, int m, C v) { F[(k << lx) + m] = v; }, ex, tw, 1);
+    const double two_pi = 2.0 * M_PI;
+    const double kap_y = (2 * y == Ky) ? 0.0 : two_pi * (double)fft_index(y, Ky) / fg.len[1];
+    // G' rho_hat of the thread's points, kept for every output
+    double re[STAGE], im[STAGE];
+    double e = 0.0;
+#pragma unroll
+    for (int u = 0; u < STAGE; ++u) {
+        const int i = threadIdx.x + u * FFT_THREADS;
+        const int m = i & (xc - 1);
+        re[u] = im[u] = 0.0;
+        if (i < cells && m < nx) {
+            const double rx = (double)F[i].x, ry = (double)F[i].y;
+            if (MODE != 2) {
+                const int ix = x0 + m;
+                const bool edge = (ix == 0) || (2 * ix == fg.K[0]);
+                e += (edge ? 0.5 : 1.0) * gk[u] * (rx * rx + ry * ry);
+            }
+            re[u] = gk[u] * rx;
+            im[u] = gk[u] * ry;
+        }
+    }
+    constexpr int NOUT = (MODE == 0) ? 3 : 1;
+    for (int c = 0; c < NOUT; ++c) {
+#pragma unroll
+        for (int u = 0; u < STAGE; ++u) {
+            const int i = threadIdx.x + u * FFT_THREADS;
+            if (i < cells) {
+                const int n = i >> lx, m = i & (xc - 1);
+                C p;
+                if (MODE == 0) {
+                    const int ix = x0 + m;
+                    double kap;
+                    if (c == 0)
+                        kap = (2 * ix == fg.K[0]) ? 0.0 : two_pi * (double)fft_index(ix, fg.K[0]) / fg.len[0];
+                    else if (c == 1)
+                        kap = kap_y;
+                    else
+                        kap = (2 * n == KZ) ? 0.0 : two_pi * (double)fft_index(n, KZ) / fg.len[2];
+                    // -i kappa (re + i im) = kappa im - i kappa re
+                    p = C{(R)(kap * im[u]), (R)(-kap * re[u])};
+                } else {
+                    p = C{(R)re[u], (R)im[u]};
+                }
+                U[i] = p;
+            }
+        }
+        __syncthreads();
+        C* out = spec + (size_t)c * fg.slot + (size_t)y * fg.nxp + x0;
+        fft2<KZ, true, R>(
+            xc, [&](int n, int m) { return U[(n << lx) + m]; },
+            [&](int k, int m, C v) {
+                if (m < nx) out[k * plane + m] = v;
+            },
+            ex, tw, 1);
+    }
+    if (MODE != 2) {
+        for (int d = 32; d > 0; d >>= 1) e += __shfl_down(e, d, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+            epart[blockIdx.x] = s;
+        }
+    }
+}
+
+// Pass 5.  Rows of the half spectrum back to real rows: with
+//   Z'_k = (X_k + conj X_{NC-k}) + i W^-k (X_k - conj X_{NC-k}),
+// the inverse transform of Z' (length NC) is x_2n + i x_2n+1.
+template <typename R, int NC>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __restrict__ spec, R* __restrict__ out,
+                                                           int nxp, int nrows, int rows, long long spec_stride,
+                                                           long long out_stride, const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    constexpr int Kx = 2 * NC, nxh = NC + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = rows + 1;
+    C* tw = (C*)smem_raw;
+    C* xs = tw + Kx;         // [rows][nxh]
+    C* s = xs + rows * nxh;  // [NC][P]
+    C* ex = s + NC * P;      // [NC * rows]
+    load_table(tw, twg, Kx);
+    const int r0 = blockIdx.x * rows;
+    const int nr = min(rows, nrows - r0);
+    const C* src = spec + blockIdx.y * spec_stride + (size_t)r0 * nxp;
+    staged_copy<C>(
+        rows * nxh,
+        [&](int i) {
+            const int m = i / nxh, k = i - m * nxh;
+            return (m < nr) ? src[(size_t)m * nxp + k] : C{R(0), R(0)};
+        },
+        [&](int i, C v) { xs[i] = v; });
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows * NC; i += blockDim.x) {
+        const int k = i / rows, m = i - k * rows;
+        const C xa = xs[m * nxh + k];
+        const C xb = xs[m * nxh + NC - k];  // used conjugated
+        const C sm = C{xa.x + xb.x, xa.y - xb.y};
+        const C d = C{xa.x - xb.x, xa.y + xb.y};
+        const C w = C{tw[k].x, -tw[k].y};  // W^-k
+        const C dw = cmul(d, w);
+        s[k * P + m] = C{sm.x - dw.y, sm.y + dw.x};
+    }
+    __syncthreads();
+    fft2<NC, true, R>(
+        rows, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, ex, tw, 2);
+    C* dst = (C*)(out + blockIdx.y * out_stride + (size_t)r0 * Kx);
+    for (int i = threadIdx.x; i < nr * NC; i += blockDim.x) {
+        const int m = i / NC, n = i - m * NC;
+        dst[i] = s[n * P + m];
+    }
+}
+
+// Twiddle tables of the three axes, tw_d[i] = exp(-2 pi i * i / K_d), in FP64
+// and rounded once to R.
+template <typename R>
+__global__ void k_fft_twiddles(Cplx<R>* __restrict__ tw, int Kx, int Ky, int Kz)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = Kx + Ky + Kz;
+    if (i >= total) return;
+    const int K = (i < Kx) ? Kx : (i < Kx + Ky ? Ky : Kz);
+    const int j = (i < Kx) ? i : (i < Kx + Ky ? i - Kx : i - Kx - Ky);
+    const double t = 2.0 * (double)j / (double)K;
+    tw[i] = Cplx<R>{(R)cospi(t), (R)(-sinpi(t))};
+}
+
+bool pow2_in(int k, int lo, int hi) { return k >= lo && k <= hi && (k & (k - 1)) == 0; }
+
+FftGeo make_fgeo(const pppm_plan_s* pl)
+{
+    FftGeo fg{};
+    for (int d = 0; d < 3; ++d) {
+        fg.K[d] = pl->geo.K[d];
+        fg.len[d] = pl->p.box_len[d];
+    }
+    fg.nxh = fg.K[0] / 2 + 1;
+    fg.nxp = pl->fft_pitch;
+    fg.slot = pl->spec_len;
+    return fg;
+}
+
+// ---- dispatch over the transform lengths ----
+
+struct Ctx {
+    pppm_plan_s* pl;
+    FftGeo fg;
+    int mode, nout;
+    void* A;      // Cplx<R>[slot]: x-y transformed mesh charge
+    void* spec;   // Cplx<R>[nout * slot]
+    void* field;  // R[nout * ncell]
+    const void* tw;
+};
+
+template <typename R, template <typename, int> class Launch>
+bool by_length(int N, const Ctx& c)
+{
+    switch (N) {
+    case 4: Launch<R, 4>::go(c); return true;
+    case 8: Launch<R, 8>::go(c); return true;
+    case 16: Launch<R, 16>::go(c); return true;
+    case 32: Launch<R, 32>::go(c); return true;
+    case 64: Launch<R, 64>::go(c); return true;
+    case 128: Launch<R, 128>::go(c); return true;
+    case 256: Launch<R, 256>::go(c); return true;
+    case 512:
+        if constexpr (sizeof(R) == 4) {
+            Launch<R, 512>::go(c);
+            return true;
+        }
+        return false;
+    case 1024:
+        if constexpr (sizeof(R) == 4) {
+            Launch<R, 1024>::go(c);
+            return true;
+        }
+        return false;
+    default: return false;
+    }
+}
+
+template <typename R, int NC> struct XFwd {
+    static void go(const Ctx& c)
+    {
+        const int nrows = c.fg.K[1] * c.fg.K[2], rows = c.pl->fx_rows;
+        const size_t lds = sizeof(Cplx<R>) * (2 * NC + (size_t)NC * (rows + 1) + (size_t)NC * rows);
+        k_fft_x_fwd<R, NC><<<(nrows + rows - 1) / rows, FFT_THREADS, lds, c.pl->stream>>>(
+            (const R*)c.pl->rho, (Cplx<R>*)c.A, c.fg.nxp, nrows, rows, (const Cplx<R>*)c.tw);
+    }
+};
+template <typename R, int NC> struct XInv {
+    static void go(const Ctx& c)
+    {
+        const int nrows = c.fg.K[1] * c.fg.K[2], rows = c.pl->fx_rows;
+        const size_t lds =
+            sizeof(Cplx<R>) * (2 * NC + (size_t)rows * (NC + 1) + (size_t)NC * (rows + 1) + (size_t)NC * rows);
+        k_fft_x_inv<R, NC><<<dim3((nrows + rows - 1) / rows, c.nout), FFT_THREADS, lds, c.pl->stream>>>(
+            (const Cplx<R>*)c.spec, (R*)c.field, c.fg.nxp, nrows, rows, c.fg.slot, c.pl->ncell, (const Cplx<R>*)c.tw);
+    }
+};
+template <typename R, int KY> struct YFwd {
+    static void go(const Ctx& c)
+    {
+        const int xc = c.pl->fy_xc, nch = (c.fg.nxh + xc - 1) / xc;
+        const size_t lds = sizeof(Cplx<R>) * (KY + (size_t)KY * xc);
+        k_fft_y<R, KY, false><<<dim3(c.fg.K[2] * nch, 1), FFT_THREADS, lds, c.pl->stream>>>(
+            (Cplx<R>*)c.A, c.fg.nxh, c.fg.nxp, xc, nch, 0, (const Cplx<R>*)c.tw + c.fg.K[0]);
+    }
+};
+template <typename R, int KY> struct YInv {
+    static void go(const Ctx& c)
+    {
+        const int xc = c.pl->fy_xc, nch = (c.fg.nxh + xc - 1) / xc;
+        const size_t lds = sizeof(Cplx<R>) * (KY + (size_t)KY * xc);
+        k_fft_y<R, KY, true><<<dim3(c.fg.K[2] * nch, c.nout), FFT_THREADS, lds, c.pl->stream>>>(
+            (Cplx<R>*)c.spec, c.fg.nxh, c.fg.nxp, xc, nch, c.fg.slot, (const Cplx<R>*)c.tw + c.fg.K[0]);
+    }
+};
+template <typename R, int KZ> struct ZSolve {
+    static void go(const Ctx& c)
+    {
+        const int xc = c.pl->fz_xc, nch = (c.fg.nxh + xc - 1) / xc;
+        const size_t lds = sizeof(Cplx<R>) * (KZ + 3 * (size_t)KZ * xc);
+        const dim3 grid(c.fg.K[1] * nch);
+        const Cplx<R>* tw = (const Cplx<R>*)c.tw + c.fg.K[0] + c.fg.K[1];
+        const Cplx<R>* A = (const Cplx<R>*)c.A;
+        Cplx<R>* spec = (Cplx<R>*)c.spec;
+        switch (c.mode) {
+        case 0:
+            k_fft_z_solve<R, KZ, 0><<<grid, FFT_THREADS, lds, c.pl->stream>>>(A, spec, c.pl->G, c.pl->epart, c.fg, xc,
+                                                                             nch, tw);
+            break;
+        case 1:
+            k_fft_z_solve<R, KZ, 1><<<grid, FFT_THREADS, lds, c.pl->stream>>>(A, spec, c.pl->G, c.pl->epart, c.fg, xc,
+                                                                             nch, tw);
+            break;
+        default:
+            k_fft_z_solve<R, KZ, 2><<<grid, FFT_THREADS, lds, c.pl->stream>>>(A, spec, c.pl->G, c.pl->epart, c.fg, xc,
+                                                                             nch, tw);
+            break;
+        }
+    }
+};
+
+// mode: 0 ik forward (three fields), 1 ad forward (potential), 2 potential
+// alone (into spectrum / mesh slot `slot`).
+template <typename R>
+hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot)
+{
+    Ctx c{};
+    c.pl = pl;
+    c.fg = make_fgeo(pl);
+    c.mode = mode;
+    c.nout = (mode == 0) ? 3 : 1;
+    c.A = pl->rho_hat;
+    c.spec = (Cplx<R>*)pl->spec + (size_t)slot * pl->spec_len;
+    c.field = (R*)pl->field + (size_t)slot * pl->ncell;
+    c.tw = pl->fft_tw;
+    const int Nc = c.fg.K[0] / 2;
+    // every length was checked at plan creation (own_fft_supported)
+    if (mode != 2) {
+        if (!by_length<R, XFwd>(Nc, c) || !by_length<R, YFwd>(c.fg.K[1], c)) return hipErrorInvalidValue;
+    }
+    if (!by_length<R, ZSolve>(c.fg.K[2], c) || !by_length<R, YInv>(c.fg.K[1], c) || !by_length<R, XInv>(Nc, c))
+        return hipErrorInvalidValue;
+    if (mode != 2) pl->epart_blocks = pl->fz_blocks;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool own_fft_supported(const int K[3], bool mixed)
+{
+    const int hi = mixed ? 1024 : 256;  // FP64: register stages of at most 16 values
+    return pow2_in(K[0], 8, hi) && pow2_in(K[1], 8, hi) && pow2_in(K[2], 8, hi);
+}
+
+// Launch shapes: about `target` complex values per block, fewer when that
+// leaves too few blocks; x columns per block stay powers of two.
+void own_fft_shapes(pppm_plan_s* pl)
+{
+    const int Kx = pl->geo.K[0], Ky = pl->geo.K[1], Kz = pl->geo.K[2];
+    const int nxh = Kx / 2 + 1, Nc = Kx / 2;
+    const int target = pl->mixed ? 2048 : 1024;
+    const int nrows = Ky * Kz;
+    int rows = target / Nc > 0 ? target / Nc : 1;
+    while (rows > 1 && (nrows + rows - 1) / rows < 512) rows /= 2;
+    pl->fx_rows = rows;
+    int xy = target / Ky > 0 ? target / Ky : 1;
+    if (xy > 16) xy = 16;
+    while (xy > 4 && Kz * ((nxh + xy - 1) / xy) < 512) xy /= 2;
+    pl->fy_xc = xy;
+    int xz = target / Kz > 0 ? target / Kz : 1;
+    if (xz > 16) xz = 16;
+    while (xz > 4 && Ky * ((nxh + xz - 1) / xz) < 512) xz /= 2;
+    pl->fz_xc = xz;
+    pl->fz_blocks = Ky * ((nxh + xz - 1) / xz);
+    const int per_line = 128 / (pl->mixed ? 8 : 16);
+    pl->fft_pitch = (nxh + per_line - 1) / per_line * per_line;
+    pl->spec_len = (int64_t)Kz * Ky * pl->fft_pitch;
+}
+
+// The z pass keeps each thread's points in registers.
+bool own_fft_shapes_ok(const pppm_plan_s* pl)
+{
+    return (size_t)pl->geo.K[2] * pl->fz_xc <= (size_t)STAGE * FFT_THREADS;
+}
+
+size_t own_fft_lds_max(const pppm_plan_s* pl)
+{
+    const size_t csz = pl->mixed ? 8 : 16;
+    const int Kx = pl->geo.K[0], Ky = pl->geo.K[1], Kz = pl->geo.K[2];
+    const int Nc = Kx / 2;
+    const size_t rows = pl->fx_rows;
+    const size_t x_inv = csz * (Kx + rows * (Nc + 1) + (size_t)Nc * (rows + 1) + (size_t)Nc * rows);
+    const size_t y = csz * (Ky + (size_t)Ky * pl->fy_xc);
+    const size_t z = csz * (Kz + 3 * (size_t)Kz * pl->fz_xc);
+    size_t m = x_inv > y ? x_inv : y;
+    return m > z ? m : z;
+}
+
+hipError_t launch_own_fft_twiddles(pppm_plan_s* pl)
+{
+    const int total = pl->geo.K[0] + pl->geo.K[1] + pl->geo.K[2];
+    const int blocks = (total + 255) / 256;
+    if (pl->mixed)
+        k_fft_twiddles<float><<<blocks, 256, 0, pl->stream>>>((Cplx<float>*)pl->fft_tw, pl->geo.K[0], pl->geo.K[1],
+                                                              pl->geo.K[2]);
+    else
+        k_fft_twiddles<double><<<blocks, 256, 0, pl->stream>>>((Cplx<double>*)pl->fft_tw, pl->geo.K[0], pl->geo.K[1],
+                                                               pl->geo.K[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only)
+{
+    const int mode = phi_only ? 2 : (pl->p.diff == PPPM_DIFF_IK ? 0 : 1);
+    // the potential of an ik plan goes to the slot after its three fields
+    const int slot = phi_only ? (pl->p.diff == PPPM_DIFF_IK ? 3 : 0) : 0;
+    return pl->mixed ? run_own_poisson<float>(pl, mode, slot) : run_own_poisson<double>(pl, mode, slot);
+}
+
+}  // namespace pppm

@@ -9,7 +9,10 @@
 // R(k) = 4 pi exp(-k^2/4g^2) / k^2 and aliases k_m = k + 2 pi m / h, |m_d| <= 2,
 //   ik: G = sum_m U^2(k_m) (k . k_m) R(k_m) / (|k|^2 [sum_m U^2(k_m)]^2)
 //   ad: G = sum_m U^2(k_m) |k_m|^2 R(k_m) / ([sum_m U^2(k_m)] [sum_m |k_m|^2 U^2(k_m)])
-// G(0) = 0.  The plan stores (C / V) G on the half spectrum of the real FFT.
+// G(0) = 0.  The plan stores (C / V) G on the half spectrum of the real FFT,
+// or, for the library's own transforms, on the octant k_y, k_z >= 0 of it
+// only: G is even in each wavenumber component (the alias sums are
+// symmetric), so G(k_x, -k_y, k_z) = G(k_x, k_y, k_z) and likewise in z.
 #include "device_common.h"
 
 namespace pppm {
@@ -24,6 +27,7 @@ struct KGeo {
     int nxh;        // Kx / 2 + 1
     double len[3];
     double h[3];
+    int gny, gnz;   // y and z extent of the stored G: K_y, K_z (full) or K/2 + 1 (one octant)
 };
 
 __device__ __forceinline__ void store_c(float2* p, double re, double im) { *p = make_float2((float)re, (float)im); }
@@ -38,8 +42,8 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_influence(KGeo kg, long long
     const long long idx = (long long)blockIdx.x * KSPACE_THREADS + threadIdx.x;
     if (idx >= nspec) return;
     const int ix = (int)(idx % kg.nxh);
-    const int iy = (int)((idx / kg.nxh) % kg.K[1]);
-    const int iz = (int)(idx / ((long long)kg.nxh * kg.K[1]));
+    const int iy = (int)((idx / kg.nxh) % kg.gny);
+    const int iz = (int)(idx / ((long long)kg.nxh * kg.gny));
     const int ii[3] = {ix, iy, iz};
     const double two_pi = 2.0 * M_PI;
     double kk[3];
@@ -224,7 +228,9 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_self_force_partials(KGeo kg,
             for (int m = 0; m + 2 < NA; ++m) b2[d] += u[m] * u[m + 2];
         }
         const bool edge = (ix == 0) || (2 * ix == kg.K[0]);
-        const double wg = (edge ? 1.0 : 2.0) * G[idx];
+        const int gy = (kg.gny == kg.K[1]) ? iy : min(iy, kg.K[1] - iy);
+        const int gz = (kg.gnz == kg.K[2]) ? iz : min(iz, kg.K[2] - iz);
+        const double wg = (edge ? 1.0 : 2.0) * G[((size_t)gz * kg.gny + gy) * kg.nxh + ix];
         acc[0] += wg * b1[0] * sq[1] * sq[2];
         acc[1] += wg * sq[0] * b1[1] * sq[2];
         acc[2] += wg * sq[0] * sq[1] * b1[2];
@@ -270,6 +276,8 @@ KGeo make_kgeo(const pppm_plan_s* pl)
         kg.h[d] = pl->geo.h[d];
     }
     kg.nxh = kg.K[0] / 2 + 1;
+    kg.gny = pl->own_fft ? kg.K[1] / 2 + 1 : kg.K[1];
+    kg.gnz = pl->own_fft ? kg.K[2] / 2 + 1 : kg.K[2];
     return kg;
 }
 
@@ -295,9 +303,10 @@ hipError_t launch_influence(pppm_plan_s* pl)
 {
     const KGeo kg = make_kgeo(pl);
     const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
-    const long long blocks = (pl->nspec + KSPACE_THREADS - 1) / KSPACE_THREADS;
+    const long long ng = (long long)kg.nxh * kg.gny * kg.gnz;
+    const long long blocks = (ng + KSPACE_THREADS - 1) / KSPACE_THREADS;
     k_influence<<<(unsigned)blocks, KSPACE_THREADS, 0, pl->stream>>>(
-        kg, pl->nspec, pl->p.order, pl->p.g_ewald, (int)pl->p.diff, pl->p.coulomb_c / V, pl->G);
+        kg, ng, pl->p.order, pl->p.g_ewald, (int)pl->p.diff, pl->p.coulomb_c / V, pl->G);
     return hipGetLastError();
 }
 

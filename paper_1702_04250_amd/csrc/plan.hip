@@ -347,7 +347,7 @@ void release(pppm_plan_s* pl)
     if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
     void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart, pl->hist,
                     pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags, pl->wtab,
-                    pl->sfc,   pl->fft_work};
+                    pl->sfc,   pl->fft_tw,  pl->fft_work};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -422,14 +422,19 @@ pppm_status do_make_rho(pppm_plan_s* pl, double* rho)
 pppm_status do_poisson(pppm_plan_s* pl, double* energy)
 {
     if (pl->stage < Stage::Spread) return fail(pl, PPPM_ERR_STATE, "poisson before make_rho");
-    void* in[1] = {pl->rho};
-    void* out[1] = {pl->rho_hat};
-    FFT_TRY(pl, rocfft_execute(pl->fft_fwd, in, out, pl->fft_info));
-    HIP_TRY(pl, launch_kspace(pl, false));
-    HIP_TRY(pl, launch_energy_final(pl, energy));
-    void* sin_[1] = {pl->spec};
-    void* fout[1] = {pl->field};
-    FFT_TRY(pl, rocfft_execute(pl->fft_inv, sin_, fout, pl->fft_info));
+    if (pl->own_fft) {
+        HIP_TRY(pl, launch_own_poisson(pl, false));
+        HIP_TRY(pl, launch_energy_final(pl, energy));
+    } else {
+        void* in[1] = {pl->rho};
+        void* out[1] = {pl->rho_hat};
+        FFT_TRY(pl, rocfft_execute(pl->fft_fwd, in, out, pl->fft_info));
+        HIP_TRY(pl, launch_kspace(pl, false));
+        HIP_TRY(pl, launch_energy_final(pl, energy));
+        void* sin_[1] = {pl->spec};
+        void* fout[1] = {pl->field};
+        FFT_TRY(pl, rocfft_execute(pl->fft_inv, sin_, fout, pl->fft_info));
+    }
     HIP_TRY(pl, hipGetLastError());
     pl->stage = Stage::Solved;
     pl->phi_valid = (pl->p.diff == PPPM_DIFF_AD);
@@ -509,16 +514,26 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
     const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
     const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
+    // power-of-two meshes whose transform blocks fit in LDS use the library's
+    // own Poisson passes
+    pl->own_fft = own_fft_supported(g.K, pl->mixed);
+    if (pl->own_fft) {
+        own_fft_shapes(pl);
+        if (!own_fft_shapes_ok(pl) || own_fft_lds_max(pl) + LDS_STATIC > pl->lds_limit) pl->own_fft = false;
+    }
+    const int64_t epart_len = (pl->own_fft && pl->fz_blocks > 2048) ? pl->fz_blocks : 2048;
+    if (!pl->own_fft) pl->spec_len = pl->nspec;
+    const int64_t g_len = pl->own_fft ? (int64_t)(g.K[0] / 2 + 1) * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1) : pl->nspec;
     if ((st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->qpart, 3 * map_blocks * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->rho, pl->ncell * pl->rsize)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->rho_hat, pl->nspec * csz)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->nspec * csz)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho_hat, pl->spec_len * csz)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->spec_len * csz)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->field, (pl->ncomp + 1) * pl->ncell * pl->rsize)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->G, pl->nspec * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->epart, 2048 * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->G, g_len * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->epart, epart_len * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
@@ -543,7 +558,16 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
             return bail(PPPM_ERR_HIP);
         }
     }
-    if ((st = make_fft_plans(pl)) != PPPM_OK) return bail(st);
+    if (pl->own_fft) {
+        if ((st = dmalloc(pl, &pl->fft_tw, (size_t)(g.K[0] + g.K[1] + g.K[2]) * csz)) != PPPM_OK) return bail(st);
+        e = launch_own_fft_twiddles(pl);
+        if (e != hipSuccess) {
+            pl->last_error = std::string("twiddle tables: ") + hipGetErrorString(e);
+            return bail(PPPM_ERR_HIP);
+        }
+    } else if ((st = make_fft_plans(pl)) != PPPM_OK) {
+        return bail(st);
+    }
     if ((params->flags & PPPM_FLAG_WEIGHT_TABLE) && (st = build_weight_table(pl)) != PPPM_OK) return bail(st);
 
     pl->spread_cfg.threads = 1024;
@@ -628,11 +652,15 @@ pppm_status pppm_energy_backward(pppm_plan plan, const double* grad_energy, int6
     // gradient belongs to the same positions as the retained potential.
     if (!pl->phi_valid) {
         // ik plan: the potential mesh of the same influence function
-        HIP_TRY(pl, launch_kspace(pl, true));
-        const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
-        void* sin_[1] = {(char*)pl->spec + 3 * pl->nspec * csz};
-        void* fout[1] = {(char*)pl->field + 3 * pl->ncell * pl->rsize};
-        FFT_TRY(pl, rocfft_execute(pl->fft_inv1, sin_, fout, pl->fft_info));
+        if (pl->own_fft) {
+            HIP_TRY(pl, launch_own_poisson(pl, true));
+        } else {
+            HIP_TRY(pl, launch_kspace(pl, true));
+            const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
+            void* sin_[1] = {(char*)pl->spec + 3 * pl->nspec * csz};
+            void* fout[1] = {(char*)pl->field + 3 * pl->ncell * pl->rsize};
+            FFT_TRY(pl, rocfft_execute(pl->fft_inv1, sin_, fout, pl->fft_info));
+        }
         pl->phi_valid = true;
     }
     HIP_TRY(pl, launch_gather(pl, GATHER_ADJOINT, grad_pos, grad_q, grad_energy));

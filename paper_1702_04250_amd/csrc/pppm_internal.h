@@ -90,7 +90,7 @@ struct pppm_plan_s {
     void* rho_hat = nullptr;   // [nspec] complex R
     void* spec = nullptr;      // [(ncomp + 1) * nspec] complex R: field spectra, then phi spectrum
     void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
-    double* G = nullptr;       // [nspec] (C / V) G(k)
+    double* G = nullptr;       // [nspec] (C / V) G(k); own transforms: [Kz/2+1][Ky/2+1][Kx/2+1] octant
     double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
     double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, max count, max |q|
     void* wtab = nullptr;      // stencil-weight table (PPPM_FLAG_WEIGHT_TABLE)
@@ -107,6 +107,15 @@ struct pppm_plan_s {
     int hist_chunk = 0;        // charges per block of the last histogram map
     int64_t epart_blocks = 0;
 
+    // Poisson step: the library's own LDS transforms (power-of-two meshes)
+    // or rocFFT plans (other sizes)
+    bool own_fft = false;
+    void* fft_tw = nullptr;    // [Kx + Ky + Kz] complex R twiddle tables (own transforms)
+    int fx_rows = 1;           // rows per block of the x passes
+    int fy_xc = 1, fz_xc = 1;  // x columns per block of the y and z passes
+    int fz_blocks = 0;         // blocks of the z pass (energy partial sums)
+    int fft_pitch = 0;         // row pitch of the own transforms' spectra (complex values)
+    int64_t spec_len = 0;      // elements of one spectrum: nspec (rocFFT) or Kz Ky fft_pitch (own)
     rocfft_plan fft_fwd = nullptr;   // D2Z of rho
     rocfft_plan fft_inv = nullptr;   // C2R batch ncomp
     rocfft_plan fft_inv1 = nullptr;  // C2R batch 1 (phi of an ik plan)
@@ -139,6 +148,12 @@ int kspace_blocks(long long nspec);
 hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only);
 hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out);
 hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);
+bool own_fft_supported(const int K[3], bool mixed);
+void own_fft_shapes(pppm_plan_s* pl);
+bool own_fft_shapes_ok(const pppm_plan_s* pl);
+size_t own_fft_lds_max(const pppm_plan_s* pl);
+hipError_t launch_own_fft_twiddles(pppm_plan_s* pl);
+hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only);
 
 // LDS bytes a kernel needs for the plan's tile shape.
 size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes);

@@ -74,6 +74,18 @@ def test_config3_p5_other_forms(diff, prec, io):
 EDGE_BOX = ((-3.0, 2.0, 0.5), (11.0, 13.0, 7.5))
 
 
+@pytest.mark.parametrize("mesh", [(8, 16, 32), (32, 8, 16), (16, 64, 8), (128, 16, 8)])
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+@pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
+def test_power_of_two_meshes(mesh, diff, prec, io):
+    # meshes whose sizes are all powers of two take the library's own LDS
+    # transforms (other sizes take rocFFT): anisotropic shapes, smallest axes
+    lo = (-3.0, 1.0, 2.0)
+    length = (mesh[0] * 0.9, mesh[1] * 1.1, mesh[2] * 1.0)
+    pos, q = W.random_system(700, length, seed=mesh[0] * 7 + mesh[1], box_lo=lo)
+    run_and_check(pos, q, lo, length, mesh, 5, 0.5, 1.3, diff, prec, io, label="pow2")
+
+
 @pytest.mark.parametrize("P", [2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("mesh", [(18, 20, 13), (7, 9, 11), (32, 8, 24)])
 @pytest.mark.parametrize("diff", ["ik", "ad"])
