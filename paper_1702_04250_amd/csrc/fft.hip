@@ -136,6 +136,32 @@ template <int N> struct Split {
 // tw[i * tstride].  Every thread of the block must call it; it ends with a
 // barrier.  Tasks map m fastest so that the lanes of a wavefront touch
 // consecutive sequences.
+// Stage A of one task: v[j] holds element t + N2 j of sequence m; its
+// length-N1 transform times W_N^(t k1) goes to ex.
+template <int N1, int N2, bool INV, typename R>
+__device__ __forceinline__ void stage_a(Cplx<R>* v, int t, int m, int lm, Cplx<R>* ex, const Cplx<R>* tw,
+                                        int tstride)
+{
+    Dft<N1, INV, R>::run(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+        Cplx<R> w = tw[t * k1 * tstride];  // t k1 < N
+        if (INV) w.y = -w.y;
+        if (t != 0) v[k1] = cmul(v[k1], w);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ex[((k1 * N2 + t) << lm) + m] = v[k1];
+}
+
+// Stage B of one task: v[k2] becomes coefficient k1 + N1 k2 of sequence m.
+template <int N1, int N2, bool INV, typename R>
+__device__ __forceinline__ void stage_b(Cplx<R>* v, int k1, int m, int lm, const Cplx<R>* ex)
+{
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = ex[((k1 * N2 + t) << lm) + m];
+    Dft<N2, INV, R>::run(v);
+}
+
 template <int N, bool INV, typename R, typename Ld, typename St>
 __device__ __forceinline__ void fft2(int M, Ld ld, St st, Cplx<R>* ex, const Cplx<R>* tw, int tstride)
 {
@@ -147,23 +173,13 @@ __device__ __forceinline__ void fft2(int M, Ld ld, St st, Cplx<R>* ex, const Cpl
         C v[N1];
 #pragma unroll
         for (int j = 0; j < N1; ++j) v[j] = ld(t + N2 * j, m);
-        Dft<N1, INV, R>::run(v);
-#pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) {
-            C w = tw[t * k1 * tstride];  // t k1 < N
-            if (INV) w.y = -w.y;
-            if (t != 0) v[k1] = cmul(v[k1], w);
-        }
-#pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1) ex[((k1 * N2 + t) << lm) + m] = v[k1];
+        stage_a<N1, N2, INV, R>(v, t, m, lm, ex, tw, tstride);
     }
     __syncthreads();
     for (int task = threadIdx.x; task < N1 * M; task += blockDim.x) {
         const int m = task & (M - 1), k1 = task >> lm;
         C v[N2];
-#pragma unroll
-        for (int t = 0; t < N2; ++t) v[t] = ex[((k1 * N2 + t) << lm) + m];
-        Dft<N2, INV, R>::run(v);
+        stage_b<N1, N2, INV, R>(v, k1, m, lm, ex);
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) st(k1 + N1 * k2, m, v[k2]);
     }
@@ -279,6 +295,13 @@ __device__ __forceinline__ int fft_index(int i, int K) { return (2 * i < K) ? i 
 // G' rho_hat; MODE 2: the potential alone into spec_0 (no energy).  Energy
 // partial per block: sum w_k G' |rho_hat|^2, w_k = 1/2 on the x = 0 and
 // x Nyquist planes (their Hermitian partners are not stored) and 1 elsewhere.
+//
+// The forward transform uses the split (N1, N2) and the inverse the split
+// (N2, N1): stage B of the forward leaves each task with the coefficients
+// k1 + N1 k2, k2 < N2, which are exactly the elements stage A of the
+// inverse takes, so the multiply happens in registers between the two
+// transforms with no LDS pass of its own.  One task per thread (the host
+// keeps N1 * xc <= FFT_THREADS).
 template <typename R, int KZ, int MODE>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_solve(const Cplx<R>* __restrict__ A, Cplx<R>* __restrict__ spec,
                                                              const double* __restrict__ G,
@@ -286,92 +309,100 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_solve(const Cplx<R>* __re
                                                              const Cplx<R>* __restrict__ twg)
 {
     using C = Cplx<R>;
+    constexpr int N1 = Split<KZ>::N1, N2 = Split<KZ>::N2;
+    constexpr int NOUT = (MODE == 0) ? 3 : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[FFT_THREADS / 64];
     const int Ky = fg.K[1], nxh = fg.nxh;
     const int cells = KZ * xc;
     C* tw = (C*)smem_raw;
-    C* F = tw + KZ;    // forward transform, [n][m]
-    C* U = F + cells;  // input of an inverse transform, [n][m]
-    C* ex = U + cells;
+    C* ex = tw + KZ;  // NOUT exchange buffers of `cells` values
     load_table(tw, twg, KZ);
     const int y = blockIdx.x / nchunk, ch = blockIdx.x - y * nchunk;
     const int x0 = ch * xc, nx = min(xc, nxh - x0);
     const size_t plane = (size_t)Ky * fg.nxp;
     const C* a = A + (size_t)y * fg.nxp + x0;
     const int lx = __ffs(xc) - 1;  // xc is a power of two
-    // G octant: rows (z, y) with z <= K_z / 2, y <= K_y / 2.  The thread's
-    // values (at most STAGE points: the host keeps cells <= STAGE *
-    // FFT_THREADS) are loaded first so that their latency overlaps the
-    // forward transform.
+    // the thread's task between the transforms: sequence m, coefficients
+    // k1 + N1 k2; its influence-function values (G octant: z <= K_z / 2,
+    // y <= K_y / 2) are loaded first so that their latency overlaps the
+    // forward transform
+    const bool mid = (int)threadIdx.x < N1 * xc;
+    const int mk1 = threadIdx.x >> lx, mm = threadIdx.x & (xc - 1);
+    const bool live = mid && mm < nx;
     const int gny = Ky / 2 + 1;
     const int gy = min(y, Ky - y);
-    double gk[STAGE];
+    double gk[N2];
 #pragma unroll
-    for (int u = 0; u < STAGE; ++u) {
-        const int i = threadIdx.x + u * FFT_THREADS;
-        const int n = i >> lx, m = i & (xc - 1);
-        gk[u] = 0.0;
-        if (i < cells && m < nx) gk[u] = G[((size_t)min(n, KZ - n) * gny + gy) * nxh + x0 + m];
+    for (int k2 = 0; k2 < N2; ++k2) {
+        const int n = mk1 + N1 * k2;
+        gk[k2] = live ? G[((size_t)min(n, KZ - n) * gny + gy) * nxh + x0 + mm] : 0.0;
     }
     __syncthreads();  // twiddle table
-    fft2<KZ, false, R>(
-        xc, [&](int n, int m) { return (m < nx) ? a[n * plane + m] : C{R(0), R(0)}; },
-        [&](int k, int m, C v) { F[(k << lx) + m] = v; }, ex, tw, 1);
-    const double two_pi = 2.0 * M_PI;
-    const double kap_y = (2 * y == Ky) ? 0.0 : two_pi * (double)fft_index(y, Ky) / fg.len[1];
-    // G' rho_hat of the thread's points, kept for every output
-    double re[STAGE], im[STAGE];
-    double e = 0.0;
+    // forward, stage A: global -> registers -> ex
+    for (int task = threadIdx.x; task < N2 * xc; task += blockDim.x) {
+        const int m = task & (xc - 1), t = task >> lx;
+        C v[N1];
 #pragma unroll
-    for (int u = 0; u < STAGE; ++u) {
-        const int i = threadIdx.x + u * FFT_THREADS;
-        const int m = i & (xc - 1);
-        re[u] = im[u] = 0.0;
-        if (i < cells && m < nx) {
-            const double rx = (double)F[i].x, ry = (double)F[i].y;
-            if (MODE != 2) {
-                const int ix = x0 + m;
+        for (int j = 0; j < N1; ++j) v[j] = (m < nx) ? a[(t + N2 * j) * plane + m] : C{R(0), R(0)};
+        stage_a<N1, N2, false, R>(v, t, m, lx, ex, tw, 1);
+    }
+    __syncthreads();
+    // forward, stage B, and the k-space multiply in registers
+    C f[N2];
+    double e = 0.0;
+    if (mid) {
+        stage_b<N1, N2, false, R>(f, mk1, mm, lx, ex);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            const double rx = (double)f[k2].x, ry = (double)f[k2].y;
+            if (MODE != 2 && live) {
+                const int ix = x0 + mm;
                 const bool edge = (ix == 0) || (2 * ix == fg.K[0]);
-                e += (edge ? 0.5 : 1.0) * gk[u] * (rx * rx + ry * ry);
+                e += (edge ? 0.5 : 1.0) * gk[k2] * (rx * rx + ry * ry);
             }
-            re[u] = gk[u] * rx;
-            im[u] = gk[u] * ry;
+            f[k2] = C{(R)(gk[k2] * rx), (R)(gk[k2] * ry)};  // G' rho_hat (0 off the mesh)
         }
     }
-    constexpr int NOUT = (MODE == 0) ? 3 : 1;
-    for (int c = 0; c < NOUT; ++c) {
+    __syncthreads();  // every task has read ex
+    // inverse, stage A (split N2, N1) for each output
+    if (mid) {
+        const double two_pi = 2.0 * M_PI;
+        for (int c = 0; c < NOUT; ++c) {
+            C v[N2];
 #pragma unroll
-        for (int u = 0; u < STAGE; ++u) {
-            const int i = threadIdx.x + u * FFT_THREADS;
-            if (i < cells) {
-                const int n = i >> lx, m = i & (xc - 1);
-                C p;
+            for (int k2 = 0; k2 < N2; ++k2) {
                 if (MODE == 0) {
-                    const int ix = x0 + m;
+                    const int n = mk1 + N1 * k2, ix = x0 + mm;
                     double kap;
                     if (c == 0)
                         kap = (2 * ix == fg.K[0]) ? 0.0 : two_pi * (double)fft_index(ix, fg.K[0]) / fg.len[0];
                     else if (c == 1)
-                        kap = kap_y;
+                        kap = (2 * y == Ky) ? 0.0 : two_pi * (double)fft_index(y, Ky) / fg.len[1];
                     else
                         kap = (2 * n == KZ) ? 0.0 : two_pi * (double)fft_index(n, KZ) / fg.len[2];
                     // -i kappa (re + i im) = kappa im - i kappa re
-                    p = C{(R)(kap * im[u]), (R)(-kap * re[u])};
+                    v[k2] = C{(R)(kap * (double)f[k2].y), (R)(-kap * (double)f[k2].x)};
                 } else {
-                    p = C{(R)re[u], (R)im[u]};
+                    v[k2] = f[k2];
                 }
-                U[i] = p;
+            }
+            stage_a<N2, N1, true, R>(v, mk1, mm, lx, ex + c * cells, tw, 1);
+        }
+    }
+    __syncthreads();
+    // inverse, stage B: ex -> registers -> global
+    for (int c = 0; c < NOUT; ++c) {
+        C* out = spec + (size_t)c * fg.slot + (size_t)y * fg.nxp + x0;
+        for (int task = threadIdx.x; task < N2 * xc; task += blockDim.x) {
+            const int m = task & (xc - 1), k1 = task >> lx;
+            C v[N1];
+            stage_b<N2, N1, true, R>(v, k1, m, lx, ex + c * cells);
+            if (m < nx) {
+#pragma unroll
+                for (int k2 = 0; k2 < N1; ++k2) out[(size_t)(k1 + N2 * k2) * plane + m] = v[k2];
             }
         }
-        __syncthreads();
-        C* out = spec + (size_t)c * fg.slot + (size_t)y * fg.nxp + x0;
-        fft2<KZ, true, R>(
-            xc, [&](int n, int m) { return U[(n << lx) + m]; },
-            [&](int k, int m, C v) {
-                if (m < nx) out[k * plane + m] = v;
-            },
-            ex, tw, 1);
     }
     if (MODE != 2) {
         for (int d = 32; d > 0; d >>= 1) e += __shfl_down(e, d, 64);
@@ -542,7 +573,7 @@ template <typename R, int KZ> struct ZSolve {
     static void go(const Ctx& c)
     {
         const int xc = c.pl->fz_xc, nch = (c.fg.nxh + xc - 1) / xc;
-        const size_t lds = sizeof(Cplx<R>) * (KZ + 3 * (size_t)KZ * xc);
+        const size_t lds = sizeof(Cplx<R>) * (KZ + (size_t)(c.mode == 0 ? 3 : 1) * KZ * xc);
         const dim3 grid(c.fg.K[1] * nch);
         const Cplx<R>* tw = (const Cplx<R>*)c.tw + c.fg.K[0] + c.fg.K[1];
         const Cplx<R>* A = (const Cplx<R>*)c.A;
@@ -622,10 +653,13 @@ void own_fft_shapes(pppm_plan_s* pl)
     pl->spec_len = (int64_t)Kz * Ky * pl->fft_pitch;
 }
 
-// The z pass keeps each thread's points in registers.
+// The z pass gives each thread at most one task between its transforms.
 bool own_fft_shapes_ok(const pppm_plan_s* pl)
 {
-    return (size_t)pl->geo.K[2] * pl->fz_xc <= (size_t)STAGE * FFT_THREADS;
+    int lg = 0;
+    while ((1 << lg) < pl->geo.K[2]) ++lg;
+    const int n1 = 1 << ((lg + 1) / 2);
+    return n1 * pl->fz_xc <= FFT_THREADS;
 }
 
 size_t own_fft_lds_max(const pppm_plan_s* pl)
@@ -636,7 +670,7 @@ size_t own_fft_lds_max(const pppm_plan_s* pl)
     const size_t rows = pl->fx_rows;
     const size_t x_inv = csz * (Kx + rows * (Nc + 1) + (size_t)Nc * (rows + 1) + (size_t)Nc * rows);
     const size_t y = csz * (Ky + (size_t)Ky * pl->fy_xc);
-    const size_t z = csz * (Kz + 3 * (size_t)Kz * pl->fz_xc);
+    const size_t z = csz * (Kz + 3 * (size_t)Kz * pl->fz_xc);  // ik: three exchange buffers
     size_t m = x_inv > y ? x_inv : y;
     return m > z ? m : z;
 }
