@@ -197,16 +197,17 @@ constexpr int STAGE = 8;
 template <typename T, typename Ld, typename St>
 __device__ __forceinline__ void staged_copy(int total, Ld ld, St st)
 {
-    for (int i0 = threadIdx.x; i0 < total; i0 += STAGE * FFT_THREADS) {
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < total; i0 += STAGE * nt) {
         T v[STAGE];
 #pragma unroll
         for (int u = 0; u < STAGE; ++u) {
-            const int i = i0 + u * FFT_THREADS;
+            const int i = i0 + u * nt;
             if (i < total) v[u] = ld(i);
         }
 #pragma unroll
         for (int u = 0; u < STAGE; ++u) {
-            const int i = i0 + u * FFT_THREADS;
+            const int i = i0 + u * nt;
             if (i < total) st(i, v[u]);
         }
     }
@@ -464,6 +465,127 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
     }
 }
 
+// Passes 1 and 2 fused (mixed form, planes that fit in LDS): one z plane per
+// block.  The x = 0 and x = K_x/2 coefficients of a row are real, so they
+// travel together as one complex column Q = X_0 + i X_{K_x/2}; the y
+// transform then runs on K_x / 2 columns, and the two real columns are
+// separated afterwards by the symmetry of the transform of a real sequence,
+//   Y_0(k) = (Q(k) + conj Q(-k)) / 2,   Y_{K_x/2}(k) = (Q(k) - conj Q(-k)) / 2i.
+constexpr int XY_THREADS = 1024;
+
+template <typename R, int NC, int KY>
+__global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__ in, Cplx<R>* __restrict__ out, int nxp,
+                                                           const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    constexpr int Kx = 2 * NC, P = KY + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* twx = (C*)smem_raw;
+    C* twy = twx + Kx;
+    C* s = twy + KY;      // [NC][P]: rows transposed, then the y exchange buffer
+    C* q = s + NC * P;    // [NC * KY]: the x exchange buffer, then the plane [y][k]
+    load_table(twx, twg, Kx + KY);  // the x and y tables are adjacent
+    const C* src = (const C*)(in + (size_t)blockIdx.x * KY * Kx);
+    staged_copy<C>(
+        KY * NC, [&](int i) { return src[i]; },
+        [&](int i, C v) {
+            const int m = i / NC, n = i - m * NC;
+            s[n * P + m] = v;
+        });
+    __syncthreads();
+    fft2<NC, false, R>(
+        KY, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
+    // split into the half spectrum of each row; column 0 carries X_0 + i X_NC
+    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+        const int m = i / NC, k = i - m * NC;
+        const C za = s[k * P + m];
+        const C zb = s[(k == 0 ? 0 : NC - k) * P + m];
+        C x;
+        if (k == 0) {
+            // X_0 = Re Z_0 + Im Z_0, X_NC = Re Z_0 - Im Z_0
+            x = C{za.x + za.y, za.x - za.y};
+        } else {
+            const C fe = C{R(0.5) * (za.x + zb.x), R(0.5) * (za.y - zb.y)};
+            const C fo = C{R(0.5) * (za.y + zb.y), R(-0.5) * (za.x - zb.x)};
+            const C wf = cmul(twx[k], fo);
+            x = C{fe.x + wf.x, fe.y + wf.y};
+        }
+        q[m * NC + k] = x;
+    }
+    __syncthreads();
+    fft2<KY, false, R>(
+        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy, 1);
+    C* dst = out + (size_t)blockIdx.x * KY * nxp;
+    for (int i = threadIdx.x; i < KY * (NC + 1); i += blockDim.x) {
+        const int ky = i / (NC + 1), k = i - ky * (NC + 1);
+        C v;
+        if (k > 0 && k < NC) {
+            v = q[ky * NC + k];
+        } else {
+            const C a = q[ky * NC];
+            const C b = q[((KY - ky) & (KY - 1)) * NC];  // Q(-k), used conjugated
+            v = (k == 0) ? C{R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)}
+                         : C{R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
+        }
+        dst[(size_t)ky * nxp + k] = v;
+    }
+}
+
+// Passes 4 and 5 fused, one z plane of one output mesh per block.  The
+// x = 0 and x = K_x/2 columns are Hermitian in k_y, so their y transforms
+// are real: they go through one complex column Q = X_0 + i X_{K_x/2} and come
+// out as its real and imaginary parts.
+template <typename R, int NC, int KY>
+__global__ __launch_bounds__(XY_THREADS) void k_fft_yx_inv(const Cplx<R>* __restrict__ spec, R* __restrict__ out,
+                                                           int nxp, long long spec_stride, long long out_stride,
+                                                           const Cplx<R>* __restrict__ twg)
+{
+    using C = Cplx<R>;
+    constexpr int Kx = 2 * NC, P = KY + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* twx = (C*)smem_raw;
+    C* twy = twx + Kx;
+    C* s = twy + KY;    // [NC][P]: the y exchange buffer, then the rows transposed
+    C* q = s + NC * P;  // [KY][NC]: the plane, then the x exchange buffer
+    load_table(twx, twg, Kx + KY);
+    const C* src = spec + blockIdx.y * spec_stride + (size_t)blockIdx.x * KY * nxp;
+    staged_copy<C>(
+        KY * NC,
+        [&](int i) {
+            const int ky = i / NC, k = i - ky * NC;
+            C v = src[(size_t)ky * nxp + k];
+            if (k == 0) {
+                const C b = src[(size_t)ky * nxp + NC];
+                v = C{v.x - b.y, v.y + b.x};  // X_0 + i X_NC
+            }
+            return v;
+        },
+        [&](int i, C v) { q[i] = v; });
+    __syncthreads();
+    fft2<KY, true, R>(
+        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy, 1);
+    // fold each row into NC complex values: Z'_k = (X_k + conj X_{NC-k}) + i W^-k (X_k - conj X_{NC-k})
+    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+        const int m = i / NC, k = i - m * NC;  // k fastest: row reads of q are consecutive
+        const C w0 = q[m * NC];  // x_0 + i x_NC, both real
+        const C xa = (k == 0) ? C{w0.x, R(0)} : q[m * NC + k];
+        const C xb = (k == 0) ? C{w0.y, R(0)} : q[m * NC + NC - k];
+        const C sm = C{xa.x + xb.x, xa.y - xb.y};
+        const C d = C{xa.x - xb.x, xa.y + xb.y};
+        const C w = C{twx[k].x, -twx[k].y};  // W^-k
+        const C dw = cmul(d, w);
+        s[k * P + m] = C{sm.x - dw.y, sm.y + dw.x};
+    }
+    __syncthreads();
+    fft2<NC, true, R>(
+        KY, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
+    C* dst = (C*)(out + blockIdx.y * out_stride + (size_t)blockIdx.x * KY * Kx);
+    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+        const int m = i / NC, n = i - m * NC;
+        dst[i] = s[n * P + m];
+    }
+}
+
 // Twiddle tables of the three axes, tw_d[i] = exp(-2 pi i * i / K_d), in FP64
 // and rounded once to R.
 template <typename R>
@@ -595,6 +717,53 @@ template <typename R, int KZ> struct ZSolve {
     }
 };
 
+// Fused x-y passes: planes of NC * KY <= XY_MAX complex values (two such
+// buffers stay within the LDS of one block).
+constexpr int XY_MAX = 8192;
+
+size_t xy_lds_bytes(int nc, int ky) { return sizeof(Cplx<float>) * (2 * nc + ky + (size_t)nc * (ky + 1) + (size_t)nc * ky); }
+
+template <int NC, int KY> void xy_go(const Ctx& c, bool inverse)
+{
+    if constexpr (NC * KY <= XY_MAX) {
+        const size_t lds = xy_lds_bytes(NC, KY);
+        const Cplx<float>* tw = (const Cplx<float>*)c.tw;
+        if (!inverse)
+            k_fft_xy_fwd<float, NC, KY><<<c.fg.K[2], XY_THREADS, lds, c.pl->stream>>>(
+                (const float*)c.pl->rho, (Cplx<float>*)c.A, c.fg.nxp, tw);
+        else
+            k_fft_yx_inv<float, NC, KY><<<dim3(c.fg.K[2], c.nout), XY_THREADS, lds, c.pl->stream>>>(
+                (const Cplx<float>*)c.spec, (float*)c.field, c.fg.nxp, c.fg.slot, c.pl->ncell, tw);
+    }
+}
+
+template <int NC> bool xy_by_ky(int ky, const Ctx& c, bool inverse)
+{
+    switch (ky) {
+    case 16: xy_go<NC, 16>(c, inverse); return true;
+    case 32: xy_go<NC, 32>(c, inverse); return true;
+    case 64: xy_go<NC, 64>(c, inverse); return true;
+    case 128: xy_go<NC, 128>(c, inverse); return true;
+    case 256: xy_go<NC, 256>(c, inverse); return true;
+    case 512: xy_go<NC, 512>(c, inverse); return true;
+    default: return false;
+    }
+}
+
+bool xy_launch(const Ctx& c, bool inverse)
+{
+    const int nc = c.fg.K[0] / 2, ky = c.fg.K[1];
+    switch (nc) {
+    case 16: return xy_by_ky<16>(ky, c, inverse);
+    case 32: return xy_by_ky<32>(ky, c, inverse);
+    case 64: return xy_by_ky<64>(ky, c, inverse);
+    case 128: return xy_by_ky<128>(ky, c, inverse);
+    case 256: return xy_by_ky<256>(ky, c, inverse);
+    case 512: return xy_by_ky<512>(ky, c, inverse);
+    default: return false;
+    }
+}
+
 // mode: 0 ik forward (three fields), 1 ad forward (potential), 2 potential
 // alone (into spectrum / mesh slot `slot`).
 template <typename R>
@@ -610,12 +779,22 @@ hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot)
     c.field = (R*)pl->field + (size_t)slot * pl->ncell;
     c.tw = pl->fft_tw;
     const int Nc = c.fg.K[0] / 2;
-    // every length was checked at plan creation (own_fft_supported)
+    // every length was checked at plan creation (own_fft_supported,
+    // own_fft_shapes decides fft_xy)
+    const bool xy = pl->fft_xy && sizeof(R) == 4;
     if (mode != 2) {
-        if (!by_length<R, XFwd>(Nc, c) || !by_length<R, YFwd>(c.fg.K[1], c)) return hipErrorInvalidValue;
+        if (xy) {
+            if (!xy_launch(c, false)) return hipErrorInvalidValue;
+        } else if (!by_length<R, XFwd>(Nc, c) || !by_length<R, YFwd>(c.fg.K[1], c)) {
+            return hipErrorInvalidValue;
+        }
     }
-    if (!by_length<R, ZSolve>(c.fg.K[2], c) || !by_length<R, YInv>(c.fg.K[1], c) || !by_length<R, XInv>(Nc, c))
+    if (!by_length<R, ZSolve>(c.fg.K[2], c)) return hipErrorInvalidValue;
+    if (xy) {
+        if (!xy_launch(c, true)) return hipErrorInvalidValue;
+    } else if (!by_length<R, YInv>(c.fg.K[1], c) || !by_length<R, XInv>(Nc, c)) {
         return hipErrorInvalidValue;
+    }
     if (mode != 2) pl->epart_blocks = pl->fz_blocks;
     return hipGetLastError();
 }
@@ -648,6 +827,9 @@ void own_fft_shapes(pppm_plan_s* pl)
     while (xz > 4 && Ky * ((nxh + xz - 1) / xz) < 512) xz /= 2;
     pl->fz_xc = xz;
     pl->fz_blocks = Ky * ((nxh + xz - 1) / xz);
+    // x and y fused per plane: mixed form, 16 <= K_x / 2, K_y <= 512, plane within XY_MAX
+    pl->fft_xy = pl->mixed && Nc >= 16 && Ky >= 16 && Nc <= 512 && Ky <= 512 && Nc * Ky <= XY_MAX &&
+                 xy_lds_bytes(Nc, Ky) + 1024 <= pl->lds_limit;
     const int per_line = 128 / (pl->mixed ? 8 : 16);
     pl->fft_pitch = (nxh + per_line - 1) / per_line * per_line;
     pl->spec_len = (int64_t)Kz * Ky * pl->fft_pitch;

@@ -115,6 +115,7 @@ struct pppm_plan_s {
     int fy_xc = 1, fz_xc = 1;  // x columns per block of the y and z passes
     int fz_blocks = 0;         // blocks of the z pass (energy partial sums)
     int fft_pitch = 0;         // row pitch of the own transforms' spectra (complex values)
+    bool fft_xy = false;       // x and y passes fused per z plane (mixed form, plane fits in LDS)
     int64_t spec_len = 0;      // elements of one spectrum: nspec (rocFFT) or Kz Ky fft_pitch (own)
     rocfft_plan fft_fwd = nullptr;   // D2Z of rho
     rocfft_plan fft_inv = nullptr;   // C2R batch ncomp
