@@ -342,9 +342,11 @@ def cpu_baseline(w, order, pos_r, q_r, budget_s=12.0):
 
 def shift_work(torch, pkg, workloads, steps, warmup):
     """Higher order on a coarser mesh (the paper's trade, its Section 2.3 and
-    the results of Section 4): for each P, the smallest K (of a list of FFT
+    the results of Section 4): for each P, the meshes (of a list of FFT
     friendly sizes) whose mixed-form ad forces are within the target RMS
-    relative error of a converged reference, and the GPU step time there.
+    relative error of a converged reference, and the fastest GPU step among
+    them (power-of-two meshes run the library's own transforms, the others
+    rocFFT, so the smallest mesh is not always the fastest).
     Reference: the FP64 form at P = 7 on a 288^3 mesh (h = 0.59 A)."""
     w = workloads.config(3)
     dev = torch.device("cuda:0")
@@ -366,23 +368,40 @@ def shift_work(torch, pkg, workloads, steps, warmup):
     ref_plan.close()
     den = float((ref ** 2).sum())
     sizes = [32, 40, 48, 56, 64, 72, 80, 96, 112, 128, 144, 160, 192, 224, 256]
+    # bring the clocks up before the first timed loop
+    warm, _ = forces(5, 128, "mixed", pos, q)
+    run_loop(torch, warm, pos, q, steps, warmup, "ad")
+    warm.close()
     rows = []
     for target in (1e-3, 1e-4):
         for P in range(3, 8):
-            chosen = None
+            # every size from the smallest one that meets the target up to
+            # the next power of two (whose Poisson step takes the library's
+            # own transforms) is timed; the fastest is reported
+            best, smallest = None, None
             for K in sizes:
+                if smallest is not None and K > smallest and (K & (K - 1)) != 0 and (smallest & (smallest - 1)) == 0:
+                    break
                 plan, f = forces(P, K, "mixed", pos, q)
                 err = float(np.sqrt(((f - ref) ** 2).sum() / den))
                 if err <= target:
                     res, _, _ = run_loop(torch, plan, pos, q, steps, warmup, "ad")
-                    chosen = {"target": target, "P": P, "K": K, "h_A": w.box_len[0] / K, "force_err": err,
-                              "step_us": 1e3 * res["ms_per_step"],
-                              "kernels_us": {k[:-3]: round(v, 2) for k, v in res.items()
-                                             if k.endswith("_us") and k != "step_us"}}
+                    row = {"target": target, "P": P, "K": K, "h_A": w.box_len[0] / K, "force_err": err,
+                           "step_us": 1e3 * res["ms_per_step"],
+                           "kernels_us": {k[:-3]: round(v, 2) for k, v in res.items()
+                                          if k.endswith("_us") and k != "step_us"}}
+                    if smallest is None:
+                        smallest = K
+                    if best is None or row["step_us"] < best["step_us"]:
+                        best = row
                     plan.close()
-                    break
+                    if (K & (K - 1)) == 0:
+                        break
+                    continue
                 plan.close()
-            rows.append(chosen or {"target": target, "P": P, "K": None})
+            if best is not None:
+                best["smallest_K_meeting_target"] = smallest
+            rows.append(best or {"target": target, "P": P, "K": None})
             print(json.dumps(rows[-1]), flush=True)
     return rows
 
