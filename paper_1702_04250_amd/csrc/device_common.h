@@ -17,13 +17,14 @@ namespace pppm {
 constexpr int NUM_XCD = 8;
 constexpr int XCD_CHUNK = 4;
 
+template <int CHUNK = XCD_CHUNK>
 __device__ __forceinline__ int xcd_remap(int wg, int nwg)
 {
-    constexpr int ROUND = NUM_XCD * XCD_CHUNK;
+    constexpr int ROUND = NUM_XCD * CHUNK;
     const int nfull = nwg / ROUND * ROUND;
     if (wg >= nfull) return wg;
     const int x = wg % NUM_XCD, local = wg / NUM_XCD;
-    return (local / XCD_CHUNK) * ROUND + x * XCD_CHUNK + local % XCD_CHUNK;
+    return (local / CHUNK) * ROUND + x * CHUNK + local % CHUNK;
 }
 
 // Record of a binned particle: stencil start within its tile plus the

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_count(int n, int chunk, i
 // and the counts become their exclusive prefix over blocks (the block's
 // offset within the bin); the bin total goes to count[bin].
 constexpr int PREFIX_THREADS = 256;
-constexpr int PREFIX_SEGS = 4;
+constexpr int PREFIX_SEGS = 8;
 constexpr int PREFIX_BINS = PREFIX_THREADS / PREFIX_SEGS;
 constexpr int PREFIX_SEG_MAX = HIST_MAX_BLOCKS / PREFIX_SEGS;
 
@@ -352,7 +352,9 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
                                                           typename Rec<R>::T* __restrict__ rec,
                                                           int* __restrict__ perm)
 {
-    const int i = blockIdx.x * MAP_THREADS + threadIdx.x;
+    // the blocks that read one histogram row (HIST_CHUNK charges) run on one
+    // XCD, so that row is fetched into one L2 only
+    const int i = xcd_remap<HIST_CHUNK / MAP_THREADS>(blockIdx.x, gridDim.x) * MAP_THREADS + threadIdx.x;
     if (i >= n) return;
     int s[3];
     double f[3];
