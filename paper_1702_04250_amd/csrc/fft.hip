@@ -30,6 +30,7 @@
 // compile-time constants; the twiddles W_N come from per-axis tables
 // computed in FP64 at plan creation.
 #include "device_common.h"
+#include "energy_sum.h"
 
 namespace pppm {
 
@@ -423,7 +424,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_solve(const Cplx<R>* __re
 template <typename R, int NC>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __restrict__ spec, R* __restrict__ out,
                                                            int nxp, int nrows, int rows, long long spec_stride,
-                                                           long long out_stride, const Cplx<R>* __restrict__ twg)
+                                                           long long out_stride, const Cplx<R>* __restrict__ twg,
+                                                           EnergySums es, int final_sums)
 {
     using C = Cplx<R>;
     constexpr int Kx = 2 * NC, nxh = NC + 1;
@@ -463,6 +465,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
         const int m = i / NC, n = i - m * NC;
         dst[i] = s[n * P + m];
     }
+    // the z pass, which took the k-space partial sums, has completed
+    if (final_sums && blockIdx.x == 0 && blockIdx.y == 0) energy_final_block(es);
 }
 
 // Passes 1 and 2 fused (mixed form, planes that fit in LDS): one z plane per
@@ -538,7 +542,8 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__
 template <typename R, int NC, int KY>
 __global__ __launch_bounds__(XY_THREADS) void k_fft_yx_inv(const Cplx<R>* __restrict__ spec, R* __restrict__ out,
                                                            int nxp, long long spec_stride, long long out_stride,
-                                                           const Cplx<R>* __restrict__ twg)
+                                                           const Cplx<R>* __restrict__ twg, EnergySums es,
+                                                           int final_sums)
 {
     using C = Cplx<R>;
     constexpr int Kx = 2 * NC, P = KY + 1;
@@ -584,6 +589,8 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_yx_inv(const Cplx<R>* __rest
         const int m = i / NC, n = i - m * NC;
         dst[i] = s[n * P + m];
     }
+    // the z pass, which took the k-space partial sums, has completed
+    if (final_sums && blockIdx.x == 0 && blockIdx.y == 0) energy_final_block(es);
 }
 
 // Twiddle tables of the three axes, tw_d[i] = exp(-2 pi i * i / K_d), in FP64
@@ -625,6 +632,8 @@ struct Ctx {
     void* spec;   // Cplx<R>[nout * slot]
     void* field;  // R[nout * ncell]
     const void* tw;
+    EnergySums es;   // final energy sums, taken by the last pass
+    int final_sums;  // 0 for the potential alone
 };
 
 template <typename R, template <typename, int> class Launch>
@@ -670,7 +679,8 @@ template <typename R, int NC> struct XInv {
         const size_t lds =
             sizeof(Cplx<R>) * (2 * NC + (size_t)rows * (NC + 1) + (size_t)NC * (rows + 1) + (size_t)NC * rows);
         k_fft_x_inv<R, NC><<<dim3((nrows + rows - 1) / rows, c.nout), FFT_THREADS, lds, c.pl->stream>>>(
-            (const Cplx<R>*)c.spec, (R*)c.field, c.fg.nxp, nrows, rows, c.fg.slot, c.pl->ncell, (const Cplx<R>*)c.tw);
+            (const Cplx<R>*)c.spec, (R*)c.field, c.fg.nxp, nrows, rows, c.fg.slot, c.pl->ncell, (const Cplx<R>*)c.tw,
+            c.es, c.final_sums);
     }
 };
 template <typename R, int KY> struct YFwd {
@@ -733,7 +743,8 @@ template <int NC, int KY> void xy_go(const Ctx& c, bool inverse)
                 (const float*)c.pl->rho, (Cplx<float>*)c.A, c.fg.nxp, tw);
         else
             k_fft_yx_inv<float, NC, KY><<<dim3(c.fg.K[2], c.nout), XY_THREADS, lds, c.pl->stream>>>(
-                (const Cplx<float>*)c.spec, (float*)c.field, c.fg.nxp, c.fg.slot, c.pl->ncell, tw);
+                (const Cplx<float>*)c.spec, (float*)c.field, c.fg.nxp, c.fg.slot, c.pl->ncell, tw, c.es,
+                c.final_sums);
     }
 }
 
@@ -767,9 +778,12 @@ bool xy_launch(const Ctx& c, bool inverse)
 // mode: 0 ik forward (three fields), 1 ad forward (potential), 2 potential
 // alone (into spectrum / mesh slot `slot`).
 template <typename R>
-hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot)
+hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot, double* energy_out)
 {
+    if (mode != 2) pl->epart_blocks = pl->fz_blocks;
     Ctx c{};
+    c.es = energy_sums(pl, energy_out);
+    c.final_sums = (mode != 2);
     c.pl = pl;
     c.fg = make_fgeo(pl);
     c.mode = mode;
@@ -795,7 +809,6 @@ hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot)
     } else if (!by_length<R, YInv>(c.fg.K[1], c) || !by_length<R, XInv>(Nc, c)) {
         return hipErrorInvalidValue;
     }
-    if (mode != 2) pl->epart_blocks = pl->fz_blocks;
     return hipGetLastError();
 }
 
@@ -870,12 +883,13 @@ hipError_t launch_own_fft_twiddles(pppm_plan_s* pl)
     return hipGetLastError();
 }
 
-hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only)
+hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only, double* energy_out)
 {
     const int mode = phi_only ? 2 : (pl->p.diff == PPPM_DIFF_IK ? 0 : 1);
     // the potential of an ik plan goes to the slot after its three fields
     const int slot = phi_only ? (pl->p.diff == PPPM_DIFF_IK ? 3 : 0) : 0;
-    return pl->mixed ? run_own_poisson<float>(pl, mode, slot) : run_own_poisson<double>(pl, mode, slot);
+    return pl->mixed ? run_own_poisson<float>(pl, mode, slot, energy_out)
+                     : run_own_poisson<double>(pl, mode, slot, energy_out);
 }
 
 }  // namespace pppm

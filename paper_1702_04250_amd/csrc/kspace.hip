@@ -14,6 +14,7 @@
 // only: G is even in each wavenumber component (the alias sums are
 // symmetric), so G(k_x, -k_y, k_z) = G(k_x, k_y, k_z) and likewise in z.
 #include "device_common.h"
+#include "energy_sum.h"
 
 namespace pppm {
 
@@ -140,52 +141,8 @@ __global__ __launch_bounds__(KSPACE_THREADS) void k_phi_only(long long nspec, co
     }
 }
 
-// Deterministic final sums: E_mesh from the k-space partials, Q and sum q^2
-// from the particle-map partials; E_self = -C g / sqrt(pi) sum q^2,
-// E_bg = -C pi Q^2 / (2 V g^2).
-__global__ __launch_bounds__(1024) void k_energy_final(int ne, const double* __restrict__ epart, int nq,
-                                                       const double* __restrict__ qpart, double self_c,
-                                                       double bg_c, double* __restrict__ eterms,
-                                                       double* __restrict__ energy_out)
-{
-    __shared__ double red[3][16];
-    double e = 0.0, qs = 0.0, q2 = 0.0;
-    for (int i = threadIdx.x; i < ne; i += blockDim.x) e += epart[i];
-    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
-        qs += qpart[3 * i];
-        q2 += qpart[3 * i + 1];
-    }
-    for (int d = 32; d > 0; d >>= 1) {
-        e += __shfl_down(e, d, 64);
-        qs += __shfl_down(qs, d, 64);
-        q2 += __shfl_down(q2, d, 64);
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wid] = e;
-        red[1][wid] = qs;
-        red[2][wid] = q2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double E = 0.0, Q = 0.0, Q2 = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-            E += red[0][w];
-            Q += red[1][w];
-            Q2 += red[2][w];
-        }
-        const double e_self = -self_c * Q2;
-        const double e_bg = -bg_c * Q * Q;
-        const double total = E + e_self + e_bg;
-        eterms[0] = total;
-        eterms[1] = E;
-        eterms[2] = e_self;
-        eterms[3] = e_bg;
-        eterms[4] = Q;
-        eterms[5] = Q2;
-        if (energy_out) *energy_out = total;
-    }
-}
+// Deterministic final sums (energy_sum.h).
+__global__ __launch_bounds__(1024) void k_energy_final(EnergySums es) { energy_final_block(es); }
 
 // ad self-force coefficients.  A lone charge q at mesh coordinate u has the
 // mesh energy (C q^2 / 2V) sum_k G sum_{a,b} U(k_a) U(k_b) cos(2 pi (a - b).u)
@@ -283,6 +240,22 @@ KGeo make_kgeo(const pppm_plan_s* pl)
 
 }  // namespace
 
+EnergySums energy_sums(const pppm_plan_s* pl, double* energy_out)
+{
+    const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
+    const double C = pl->p.coulomb_c, g = pl->p.g_ewald;
+    EnergySums es{};
+    es.ne = (int)pl->epart_blocks;
+    es.epart = pl->epart;
+    es.nq = (int)pl->qpart_blocks;
+    es.qpart = pl->qpart;
+    es.self_c = C * g / sqrt(M_PI);
+    es.bg_c = C * M_PI / (2.0 * V * g * g);
+    es.eterms = pl->eterms;
+    es.energy_out = energy_out;
+    return es;
+}
+
 int kspace_blocks(long long nspec)
 {
     const long long b = (nspec + KSPACE_THREADS - 1) / KSPACE_THREADS;
@@ -338,12 +311,7 @@ hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only)
 
 hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out)
 {
-    const double V = pl->p.box_len[0] * pl->p.box_len[1] * pl->p.box_len[2];
-    const double C = pl->p.coulomb_c, g = pl->p.g_ewald;
-    const double self_c = C * g / sqrt(M_PI);
-    const double bg_c = C * M_PI / (2.0 * V * g * g);
-    k_energy_final<<<1, 1024, 0, pl->stream>>>((int)pl->epart_blocks, pl->epart, (int)pl->qpart_blocks, pl->qpart,
-                                               self_c, bg_c, pl->eterms, energy_out);
+    k_energy_final<<<1, 1024, 0, pl->stream>>>(energy_sums(pl, energy_out));
     return hipGetLastError();
 }
 

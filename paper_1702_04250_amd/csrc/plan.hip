@@ -423,8 +423,7 @@ pppm_status do_poisson(pppm_plan_s* pl, double* energy)
 {
     if (pl->stage < Stage::Spread) return fail(pl, PPPM_ERR_STATE, "poisson before make_rho");
     if (pl->own_fft) {
-        HIP_TRY(pl, launch_own_poisson(pl, false));
-        HIP_TRY(pl, launch_energy_final(pl, energy));
+        HIP_TRY(pl, launch_own_poisson(pl, false, energy));
     } else {
         void* in[1] = {pl->rho};
         void* out[1] = {pl->rho_hat};
@@ -653,7 +652,7 @@ pppm_status pppm_energy_backward(pppm_plan plan, const double* grad_energy, int6
     if (!pl->phi_valid) {
         // ik plan: the potential mesh of the same influence function
         if (pl->own_fft) {
-            HIP_TRY(pl, launch_own_poisson(pl, true));
+            HIP_TRY(pl, launch_own_poisson(pl, true, nullptr));
         } else {
             HIP_TRY(pl, launch_kspace(pl, true));
             const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <string>
 
+#include "energy_sum.h"
 #include "pppm.h"
 
 namespace pppm {
@@ -148,13 +149,16 @@ hipError_t launch_self_force_coef(pppm_plan_s* pl);
 int kspace_blocks(long long nspec);
 hipError_t launch_kspace(pppm_plan_s* pl, bool phi_only);
 hipError_t launch_energy_final(pppm_plan_s* pl, double* energy_out);
+EnergySums energy_sums(const pppm_plan_s* pl, double* energy_out);
 hipError_t launch_copy_terms(pppm_plan_s* pl, double* out3);
 bool own_fft_supported(const int K[3], bool mixed);
 void own_fft_shapes(pppm_plan_s* pl);
 bool own_fft_shapes_ok(const pppm_plan_s* pl);
 size_t own_fft_lds_max(const pppm_plan_s* pl);
 hipError_t launch_own_fft_twiddles(pppm_plan_s* pl);
-hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only);
+// phi_only false: the forward Poisson step, whose last pass also takes the
+// final energy sums (into the plan's terms and, if not null, energy_out).
+hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only, double* energy_out);
 
 // LDS bytes a kernel needs for the plan's tile shape.
 size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes);
