@@ -343,19 +343,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nbl
 // Scatter into binned order.  Histogram form (hist != nullptr): destination
 // = bin offset + the block's offset within the bin + rank; atomic form:
 // sub-bin offset + rank.
-template <typename TI, typename R>
-__global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __restrict__ pos,
-                                                          const TI* __restrict__ q, MapGeo g,
-                                                          const int* __restrict__ offsets,
-                                                          const int* __restrict__ slot,
-                                                          const int* __restrict__ hist, int chunk, int nbins,
-                                                          typename Rec<R>::T* __restrict__ rec,
-                                                          int* __restrict__ perm)
+// The binned record of charge i, written at dest_of(bin): stencil start
+// within the tile plus fraction per axis, and the charge.
+template <typename TI, typename R, typename Dest>
+__device__ __forceinline__ void scatter_charge(int i, const TI* __restrict__ pos, const TI* __restrict__ q,
+                                               const MapGeo& g, Dest dest_of, typename Rec<R>::T* __restrict__ rec,
+                                               int* __restrict__ perm)
 {
-    // the blocks that read one histogram row (HIST_CHUNK charges) run on one
-    // XCD, so that row is fetched into one L2 only
-    const int i = xcd_remap<HIST_CHUNK / MAP_THREADS>(blockIdx.x, gridDim.x) * MAP_THREADS + threadIdx.x;
-    if (i >= n) return;
     int s[3];
     double f[3];
 #pragma unroll
@@ -363,8 +357,7 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
         map_coord((double)pos[3 * (size_t)i + d], g.lo[d], g.h[d], g.K[d], g.shift, s[d], f[d]);
     int sl[3];
     const int bin = bin_of(g, s, sl);
-    const int dest = hist ? offsets[bin] + hist[(size_t)(i / chunk) * nbins + bin] + slot[i]
-                          : offsets[bin * NSUB + (i & (NSUB - 1))] + slot[i];
+    const int dest = dest_of(bin);
     if (g.wtab) {
         // tabulated weights: the nearest table node is chosen here, in FP64
         // (the record keeps the node's fraction, from which the kernels
@@ -379,6 +372,105 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
     r.w = (R)q[i];
     rec[dest] = r;
     perm[dest] = i;
+}
+
+template <typename TI, typename R>
+__global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __restrict__ pos,
+                                                          const TI* __restrict__ q, MapGeo g,
+                                                          const int* __restrict__ offsets,
+                                                          const int* __restrict__ slot,
+                                                          const int* __restrict__ hist, int chunk, int nbins,
+                                                          typename Rec<R>::T* __restrict__ rec,
+                                                          int* __restrict__ perm)
+{
+    // the blocks that read one histogram row (HIST_CHUNK charges) run on one
+    // XCD, so that row is fetched into one L2 only
+    const int i = xcd_remap<HIST_CHUNK / MAP_THREADS>(blockIdx.x, gridDim.x) * MAP_THREADS + threadIdx.x;
+    if (i >= n) return;
+    scatter_charge<TI, R>(
+        i, pos, q, g,
+        [&](int bin) {
+            return hist ? offsets[bin] + hist[(size_t)(i / chunk) * nbins + bin] + slot[i]
+                        : offsets[bin * NSUB + (i & (NSUB - 1))] + slot[i];
+        },
+        rec, perm);
+}
+
+// Histogram form with at most FUSED_SCAN_MAX_BINS bins: one block per
+// histogram chunk scans the bin totals itself (a few KiB, read from L2)
+// into LDS and scatters its chunk with them; block 0 also publishes
+// offsets[0 .. nbins] and the statistics, as the single-block scan would.
+// This saves that kernel's launch.
+constexpr int FUSED_SCAN_MAX_BINS = 8192;
+
+template <typename TI, typename R>
+__global__ __launch_bounds__(HIST_THREADS) void k_scatter_scan(int n, int chunk, int nbins, const TI* __restrict__ pos,
+                                                                const TI* __restrict__ q, MapGeo g,
+                                                                const int* __restrict__ count,
+                                                                int* __restrict__ offsets,
+                                                                const int* __restrict__ slot,
+                                                                const int* __restrict__ hist, int nqblocks,
+                                                                const double* __restrict__ qpart,
+                                                                double* __restrict__ stats,
+                                                                typename Rec<R>::T* __restrict__ rec,
+                                                                int* __restrict__ perm)
+{
+    extern __shared__ int loff[];  // [nbins] exclusive prefix of the bin totals
+    __shared__ int scratch[17];
+    __shared__ double smax[2][HIST_THREADS / 64];
+    constexpr int PER = FUSED_SCAN_MAX_BINS / HIST_THREADS;
+    const int per = (nbins + HIST_THREADS - 1) / HIST_THREADS;  // <= PER
+    const int j0 = threadIdx.x * per;
+    int c[PER];
+    int sum = 0, mc = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        c[u] = (u < per && j0 + u < nbins) ? count[j0 + u] : 0;
+        sum += c[u];
+        mc = max(mc, c[u]);
+    }
+    int total;
+    int ex = block_exclusive_scan(sum, scratch, &total);
+    const bool pub = blockIdx.x == 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (u < per && j0 + u < nbins) {
+            loff[j0 + u] = ex;
+            if (pub) offsets[j0 + u] = ex;
+            ex += c[u];
+        }
+    if (pub) {
+        // largest bin and largest |q| (from the count pass's partials)
+        double mq = 0.0;
+        for (int j = threadIdx.x; j < nqblocks; j += HIST_THREADS) mq = fmax(mq, qpart[3 * j + 2]);
+        double mcd = (double)mc;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mcd = fmax(mcd, __shfl_down(mcd, d, 64));
+            mq = fmax(mq, __shfl_down(mq, d, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            smax[0][threadIdx.x >> 6] = mcd;
+            smax[1][threadIdx.x >> 6] = mq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double x = 0.0, y = 0.0;
+            for (int w = 0; w < HIST_THREADS / 64; ++w) {
+                x = fmax(x, smax[0][w]);
+                y = fmax(y, smax[1][w]);
+            }
+            stats[0] = x;
+            stats[1] = y;
+            offsets[nbins] = total;
+        }
+    }
+    __syncthreads();
+    const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    const int* __restrict__ row = hist + (size_t)blockIdx.x * nbins;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += HIST_THREADS)
+        scatter_charge<TI, R>(
+            i, pos, q, g, [&](int bin) { return loff[bin] + row[bin] + slot[i]; }, rec, perm);
 }
 
 inline int grid_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
@@ -407,8 +499,9 @@ hipError_t launch_map_count(pppm_plan_s* pl, int64_t n, const void* pos, const v
                 pl->qpart, pl->flags);
         k_hist_prefix<<<grid_for(nbins, PREFIX_BINS), PREFIX_THREADS, 0, pl->stream>>>(nbins, nb, pl->hist,
                                                                                           pl->count);
-        k_scan_single<<<1, SSCAN_THREADS, 0, pl->stream>>>(nbins, pl->count, pl->offsets, nb, pl->qpart,
-                                                           pl->eterms + 6);
+        if (nbins > FUSED_SCAN_MAX_BINS)  // else the scatter scans (k_scatter_scan)
+            k_scan_single<<<1, SSCAN_THREADS, 0, pl->stream>>>(nbins, pl->count, pl->offsets, nb, pl->qpart,
+                                                               pl->eterms + 6);
         return hipGetLastError();
     }
     const int blocks = grid_for(n, MAP_THREADS);
@@ -434,8 +527,27 @@ hipError_t launch_scan(pppm_plan_s* pl)
     return hipGetLastError();
 }
 
+template <typename TI, typename R>
+void launch_scatter_scan(pppm_plan_s* pl, int64_t n, const void* pos, const void* q)
+{
+    const int nbins = (int)pl->nbins;
+    k_scatter_scan<TI, R><<<pl->hist_blocks, HIST_THREADS, (size_t)nbins * sizeof(int), pl->stream>>>(
+        (int)n, pl->hist_chunk, nbins, (const TI*)pos, (const TI*)q, pl->geo, pl->count, pl->offsets, pl->slot,
+        pl->hist, (int)pl->qpart_blocks, pl->qpart, pl->eterms + 6, (typename Rec<R>::T*)pl->records, pl->perm);
+}
+
 hipError_t launch_scatter(pppm_plan_s* pl, int64_t n, const void* pos, const void* q)
 {
+    if (pl->geo.bin_stride == 1 && pl->nbins <= FUSED_SCAN_MAX_BINS) {
+        // also publishes the offsets when n == 0 (one block at least)
+        const bool f32io = pl->p.io_dtype == PPPM_F32;
+        if (pl->mixed)
+            f32io ? launch_scatter_scan<float, float>(pl, n, pos, q) : launch_scatter_scan<double, float>(pl, n, pos, q);
+        else
+            f32io ? launch_scatter_scan<float, double>(pl, n, pos, q)
+                  : launch_scatter_scan<double, double>(pl, n, pos, q);
+        return hipGetLastError();
+    }
     const int blocks = grid_for(n, MAP_THREADS);
     if (blocks == 0) return hipGetLastError();
     const bool f32io = pl->p.io_dtype == PPPM_F32;
