@@ -245,8 +245,13 @@ class Timer:
         self.stream = stream
         self.pairs = {}
 
+    def preallocate(self, n):
+        """Create n events now, so that marks inside a timed loop do not."""
+        self.pool = [self.torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
     def mark(self):
-        e = self.torch.cuda.Event(enable_timing=True)
+        pool = getattr(self, "pool", None)
+        e = pool.pop() if pool else self.torch.cuda.Event(enable_timing=True)
         e.record(self.stream)
         return e
 
@@ -296,16 +301,30 @@ def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False, flush=Non
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        # the timed region: `steps` steps with events only at its two ends
+        # (a pair of events around every call costs the stream about 20 us
+        # per step on top of the work)
         timer = Timer(torch, stream)
         start = timer.mark()
         t0 = time.perf_counter()
         for _ in range(steps):
             if flush is not None:
                 flush.add_(1.0)
-            step(timer)
+            step()
         end = timer.mark()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # the per-call breakdown: the same number of steps again, each call
+        # between its own pair of events (after a few untimed steps, so the
+        # pause of the synchronisation above does not land in the first call)
+        for _ in range(3):
+            step()
+        timer.preallocate(6 * steps)
+        for _ in range(steps):
+            if flush is not None:
+                flush.add_(1.0)
+            step(timer)
+        torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
     res = {"ms_per_step": total_ms / steps, "wall_ms_per_step": 1e3 * wall / steps}
     for k in timer.pairs:
