@@ -82,19 +82,23 @@ def _csv_rows(folder, suffix):
 
 
 def _short(name):
-    name = name.split("(")[0]
-    for key in ("k_spread", "k_gather", "k_map_count", "k_scatter", "k_scan_reduce", "k_scan_apply",
-                "k_solve", "k_energy_final", "k_influence"):
-        if key in name:
-            return key
-    return name[:60]
+    """The library's kernel identifier (k_...) of a demangled name, else the
+    first 60 characters."""
+    import re
+
+    m = re.search(r"\b(k_[A-Za-z0-9_]+)", name.split("(")[0])
+    return m.group(1) if m else name.split("(")[0][:60]
+
+
+def _matches(name, kernel_filter):
+    return _short(name) == kernel_filter if kernel_filter.startswith("k_") else kernel_filter in name
 
 
 def _counter_per_dispatch(folder, counter, kernel_filter):
     """Mean of a counter (summed over its instances) per dispatch of the matching kernels."""
     per = {}
     for r in _csv_rows(folder, "counter_collection.csv"):
-        if r.get("Counter_Name") != counter or kernel_filter not in r.get("Kernel_Name", ""):
+        if r.get("Counter_Name") != counter or not _matches(r.get("Kernel_Name", ""), kernel_filter):
             continue
         key = r.get("Dispatch_Id") or r.get("Correlation_Id")
         per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
@@ -125,7 +129,8 @@ def summarize(folder):
     out.append("")
     out.append("| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/launch (calibrated) |")
     out.append("|---|---|---|---|")
-    for k in ("k_spread", "k_gather", "k_map_count", "k_scatter"):
+    for k in ("k_spread", "k_gather", "k_hist_count", "k_scatter_scan", "k_scatter", "k_map_count",
+              "k_fft_xy_fwd", "k_fft_z_solve", "k_fft_yx_inv"):
         f, _ = _counter_per_dispatch(os.path.join(folder, "fetch"), "FETCH_SIZE", k)
         w, _ = _counter_per_dispatch(os.path.join(folder, "write"), "WRITE_SIZE", k)
         if f is None or w is None or not cal["FETCH_SIZE"] or not cal["WRITE_SIZE"]:
