@@ -8,8 +8,10 @@
  *      fraction (the "calculation of stencil coefficients", Section 3.1);
  *   2. make_rho (the paper's Map-Charge): spread q times the order-P stencil
  *      coefficients onto a periodic mesh;
- *   3. Poisson solve in k-space by FFT (Equation 2; Section 3.2), done here
- *      with rocFFT and an influence-function multiply;
+ *   3. Poisson solve in k-space by FFT (Equation 2; Section 3.2): the
+ *      library's own transform kernels when every mesh size is a power of
+ *      two (8..1024 in the mixed form, 8..256 in FP64), rocFFT otherwise,
+ *      with the influence-function multiply and energy sums in between;
  *   4. fieldforce (the paper's Distribute-Force): gather the three field
  *      meshes (ik) or the derivative-weighted potential (ad) back to forces
  *      F_j = -q_j grad Phi (Equation 3).
@@ -38,7 +40,8 @@
  *     the caller.  The library reads or writes it only during the enqueued
  *     work and never frees or retains it.
  *   - A plan owns its scratch (binned particle records, permutation, meshes,
- *     influence function, rocFFT plans and work buffers) and frees it in
+ *     influence function, transform tables or rocFFT plans and work buffers)
+ *     and frees it in
  *     pppm_plan_destroy.
  *   - All work is enqueued on the HIP stream given at plan creation; calls
  *     return when the work is enqueued.  Results are valid after the stream
@@ -131,8 +134,9 @@ typedef struct {
 pppm_status pppm_validate(const pppm_params *params);
 
 /* Create a plan: validates params, allocates device scratch, builds the
- * influence function and rocFFT plans.  hip_stream is a hipStream_t (NULL =
- * the default stream) on the current device.  On success *out is a plan. */
+ * influence function and the transform tables or rocFFT plans.  hip_stream is
+ * a hipStream_t (NULL = the default stream) on the current device.  On
+ * success *out is a plan. */
 pppm_status pppm_plan_create(const pppm_params *params, void *hip_stream, pppm_plan *out);
 
 /* Release a plan and all its device memory.  Synchronises its stream first.

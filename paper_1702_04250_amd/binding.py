@@ -1,7 +1,7 @@
 """ctypes binding of libpppm_mi355x.so (the C ABI declared in include/pppm.h).
 
 Argument marshalling only: every step of the PPPM path runs in the library's
-HIP kernels (and rocFFT).  PyTorch supplies device memory and the stream.
+HIP kernels (and, for meshes that are not powers of two, rocFFT).  PyTorch supplies device memory and the stream.
 There is no CPU fallback: if the library is not built, or no GPU is present,
 creating a plan raises.
 """
