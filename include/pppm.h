@@ -41,8 +41,7 @@
  *     work and never frees or retains it.
  *   - A plan owns its scratch (binned particle records, permutation, meshes,
  *     influence function, transform tables or rocFFT plans and work buffers)
- *     and frees it in
- *     pppm_plan_destroy.
+ *     and frees it in pppm_plan_destroy.
  *   - All work is enqueued on the HIP stream given at plan creation; calls
  *     return when the work is enqueued.  Results are valid after the stream
  *     is synchronised (or pppm_sync).  One plan per stream; calls on one plan
