@@ -11,7 +11,10 @@
 //      energy partial sums taken, and transformed back along z.
 //   4. y, inverse, per output mesh, in place.
 //   5. x, inverse: each row's K_x / 2 + 1 coefficients are folded into
-//      K_x / 2 complex values, transformed back and unpacked into K_x reals.
+//      K_x / 2 complex values, transformed back and unpacked into K_x reals;
+//      one block of this pass also takes the final FP64 energy sums.
+// In the mixed form, planes of at most XY_MAX complex values run passes 1+2
+// and 4+5 fused, one z plane per block (k_fft_xy_fwd, k_fft_yx_inv).
 //
 // Each pass reads and writes the mesh once.  Conventions are those of the
 // library's transforms: forward sum_m rho_m exp(-i k.m h), inverse
