@@ -23,7 +23,7 @@ LIBNAME = "libpppm_mi355x.so"
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 HIP_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
@@ -36,20 +36,34 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile the library (always recompiles) and return its path."""
-    LIBDIR.mkdir(exist_ok=True)
-    sources = sorted(str(p) for p in CSRC.glob("*.hip"))
-    out = LIBDIR / LIBNAME
-    tmp = LIBDIR / (LIBNAME + ".tmp")
-    cmd = [hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *sources,
-           "-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib", "-o", str(tmp)]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed ({res.returncode})")
+        raise RuntimeError(f"hipcc failed ({res.returncode}): {cmd[-1]}")
+
+
+def build(verbose: bool = False) -> Path:
+    """Compile the library (always recompiles) and return its path.  The
+    sources compile in parallel (one hipcc per file), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    LIBDIR.mkdir(exist_ok=True)
+    objdir = LIBDIR / "obj"
+    objdir.mkdir(exist_ok=True)
+    sources = sorted(CSRC.glob("*.hip"))
+    objs = [objdir / (p.stem + ".o") for p in sources]
+    cmds = [[hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src), "-o", str(obj)]
+            for src, obj in zip(sources, objs)]
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    out = LIBDIR / LIBNAME
+    tmp = LIBDIR / (LIBNAME + ".tmp")
+    _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *map(str, objs),
+          "-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib", "-o", str(tmp)], verbose)
     os.replace(tmp, out)
     return out
 

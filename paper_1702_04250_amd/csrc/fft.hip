@@ -1,6 +1,8 @@
 // The Poisson step (Equation 2; Section 3.2) as five passes over the mesh
-// for meshes whose three sizes are powers of two (8 .. 1024 in the mixed
-// form, 8 .. 256 in FP64); other sizes use rocFFT (plan.hip).
+// for meshes whose sizes are powers of two (8 .. 1024 in the mixed form,
+// 8 .. 256 in FP64) or, in the mixed form, 2^a m with m in {3, 5, 7, 9}
+// (12 .. 448; K_x / 2 from the same list); other sizes use rocFFT
+// (plan.hip).
 //
 //   1. x, forward: each mesh row of K_x reals is packed as K_x / 2 complex
 //      values (even points real, odd points imaginary), transformed, and
@@ -29,9 +31,9 @@
 //   stage A: for each t, a length-N1 transform over j in registers, times
 //            the twiddle W_N^(t k1);
 //   stage B: for each k1, a length-N2 transform over t in registers.
-// The short transforms are unrolled radix-2 recursions whose roots are
-// compile-time constants; the twiddles W_N come from per-axis tables
-// computed in FP64 at plan creation.
+// The short transforms are unrolled mixed-radix (2, 3, 5, 7) recursions
+// whose roots are compile-time constants; the twiddles W_N come from
+// per-axis tables computed in FP64 at plan creation.
 #include "device_common.h"
 #include "energy_sum.h"
 
@@ -90,35 +92,72 @@ constexpr double root_sin(int k, int L)
     return q == 0 ? taylor_sin(x) : q == 1 ? taylor_cos(x) : q == 2 ? -taylor_sin(x) : -taylor_cos(x);
 }
 
-// v <- DFT_L(v), v[k] = sum_j v[j] exp(-+2 pi i j k / L) (INV: +), L a power
-// of two up to 32, unrolled: the halves of even and odd points, then the
-// butterflies with constant roots.
+// Smallest prime factor of L among 2, 3, 5, 7 (L is 7-smooth).
+constexpr int small_factor(int L) { return L % 2 == 0 ? 2 : L % 3 == 0 ? 3 : L % 5 == 0 ? 5 : 7; }
+
+// a * exp(-+2 pi i n / L) (INV: +) with a compile-time root; the trivial
+// roots cost no multiply
+template <bool INV, typename R>
+__device__ __forceinline__ Cplx<R> rot(Cplx<R> a, int n, int L)
+{
+    const int r = n % L;
+    if (r == 0) return a;
+    if (4 * r == L) return INV ? Cplx<R>{-a.y, a.x} : Cplx<R>{a.y, -a.x};  // -+i
+    if (2 * r == L) return Cplx<R>{-a.x, -a.y};
+    if (4 * r == 3 * L) return INV ? Cplx<R>{a.y, -a.x} : Cplx<R>{-a.y, a.x};  // +-i
+    const R c = (R)root_cos(r, L);
+    const R sn = INV ? (R)root_sin(r, L) : (R)-root_sin(r, L);
+    return Cplx<R>{c * a.x - sn * a.y, c * a.y + sn * a.x};
+}
+
+// v <- DFT_L(v), v[k] = sum_j v[j] exp(-+2 pi i j k / L) (INV: +), L
+// 7-smooth up to 32, unrolled: decimation in time by the smallest prime
+// factor p of L (p sub-transforms of the points j = i p + s, then p-point
+// butterflies), all roots compile-time constants.
 template <int L, bool INV, typename R> struct Dft {
     __device__ __forceinline__ static void run(Cplx<R>* v)
     {
-        constexpr int H = L / 2;
-        Cplx<R> e[H], o[H];
+        constexpr int p = small_factor(L), M = L / p;
+        if constexpr (p == 2) {
+            // radix 2 on two flat arrays (keeps long transforms in registers)
+            Cplx<R> e[M], o[M];
 #pragma unroll
-        for (int i = 0; i < H; ++i) {
-            e[i] = v[2 * i];
-            o[i] = v[2 * i + 1];
-        }
-        Dft<H, INV, R>::run(e);
-        Dft<H, INV, R>::run(o);
-#pragma unroll
-        for (int k = 0; k < H; ++k) {
-            const R c = (R)root_cos(k, L);
-            const R s = INV ? (R)root_sin(k, L) : (R)-root_sin(k, L);
-            Cplx<R> t;
-            if (k == 0) {
-                t = o[k];
-            } else if (4 * k == L) {  // exp(-+i pi/2)
-                t = INV ? Cplx<R>{-o[k].y, o[k].x} : Cplx<R>{o[k].y, -o[k].x};
-            } else {
-                t = Cplx<R>{c * o[k].x - s * o[k].y, c * o[k].y + s * o[k].x};
+            for (int i = 0; i < M; ++i) {
+                e[i] = v[2 * i];
+                o[i] = v[2 * i + 1];
             }
-            v[k] = Cplx<R>{e[k].x + t.x, e[k].y + t.y};
-            v[k + H] = Cplx<R>{e[k].x - t.x, e[k].y - t.y};
+            Dft<M, INV, R>::run(e);
+            Dft<M, INV, R>::run(o);
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const Cplx<R> t = rot<INV, R>(o[k], k, L);
+                v[k] = Cplx<R>{e[k].x + t.x, e[k].y + t.y};
+                v[k + M] = Cplx<R>{e[k].x - t.x, e[k].y - t.y};
+            }
+            return;
+        }
+        Cplx<R> sub[p][M];
+#pragma unroll
+        for (int j = 0; j < p; ++j)
+#pragma unroll
+            for (int i = 0; i < M; ++i) sub[j][i] = v[i * p + j];
+#pragma unroll
+        for (int j = 0; j < p; ++j) Dft<M, INV, R>::run(sub[j]);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            Cplx<R> t[p];
+#pragma unroll
+            for (int j = 0; j < p; ++j) t[j] = rot<INV, R>(sub[j][k], j * k, L);
+#pragma unroll
+            for (int q = 0; q < p; ++q) {
+                Cplx<R> acc = t[0];
+#pragma unroll
+                for (int j = 1; j < p; ++j) {
+                    const Cplx<R> u = rot<INV, R>(t[j], j * q, p);
+                    acc = Cplx<R>{acc.x + u.x, acc.y + u.y};
+                }
+                v[k + q * M] = acc;
+            }
         }
     }
 };
@@ -126,11 +165,15 @@ template <bool INV, typename R> struct Dft<1, INV, R> {
     __device__ __forceinline__ static void run(Cplx<R>*) {}
 };
 
-// Split of N into N1 N2 (N1 >= N2, both powers of two).
+// Split of N into N1 N2: N1 the smallest divisor with N1^2 >= N.
+constexpr int split_n1(int N)
+{
+    for (int d = 1; d < N; ++d)
+        if (N % d == 0 && d * d >= N) return d;
+    return N;
+}
 template <int N> struct Split {
-    static constexpr int lg = (N >= 1024) ? 10 : (N >= 512) ? 9 : (N >= 256) ? 8 : (N >= 128) ? 7 : (N >= 64) ? 6
-                              : (N >= 32) ? 5 : (N >= 16) ? 4 : (N >= 8) ? 3 : (N >= 4) ? 2 : 1;
-    static constexpr int N1 = 1 << ((lg + 1) / 2);
+    static constexpr int N1 = split_n1(N);
     static constexpr int N2 = N / N1;
 };
 
@@ -530,7 +573,7 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__
             v = q[ky * NC + k];
         } else {
             const C a = q[ky * NC];
-            const C b = q[((KY - ky) & (KY - 1)) * NC];  // Q(-k), used conjugated
+            const C b = q[((KY - ky) % KY) * NC];  // Q(-k), used conjugated
             v = (k == 0) ? C{R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)}
                          : C{R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
         }
@@ -610,8 +653,6 @@ __global__ void k_fft_twiddles(Cplx<R>* __restrict__ tw, int Kx, int Ky, int Kz)
     tw[i] = Cplx<R>{(R)cospi(t), (R)(-sinpi(t))};
 }
 
-bool pow2_in(int k, int lo, int hi) { return k >= lo && k <= hi && (k & (k - 1)) == 0; }
-
 FftGeo make_fgeo(const pppm_plan_s* pl)
 {
     FftGeo fg{};
@@ -639,31 +680,54 @@ struct Ctx {
     int final_sums;  // 0 for the potential alone
 };
 
+// Transform lengths the kernels are built for: powers of two (FP64 up to
+// 256), and in the mixed form 2^a m, m in {3, 5, 7, 9}, up to 448.  A mesh
+// axis of K points takes the length K (y, z) or K / 2 (x).
+#define PPPM_FFT_POW2(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256)
+#define PPPM_FFT_MIXED_ONLY(X)                                                                              \
+    X(512) X(1024) X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(10) X(20) X(40) X(80) X(160) X(320) X(14) \
+        X(28) X(56) X(112) X(224) X(448) X(18) X(36) X(72) X(144) X(288)
+
 template <typename R, template <typename, int> class Launch>
 bool by_length(int N, const Ctx& c)
 {
+#define PPPM_CASE(n)          \
+    case n:                   \
+        Launch<R, n>::go(c); \
+        return true;
+#define PPPM_CASE_MIXED(n)                  \
+    case n:                                 \
+        if constexpr (sizeof(R) == 4) {     \
+            Launch<R, n>::go(c);           \
+            return true;                    \
+        }                                   \
+        return false;
     switch (N) {
-    case 4: Launch<R, 4>::go(c); return true;
-    case 8: Launch<R, 8>::go(c); return true;
-    case 16: Launch<R, 16>::go(c); return true;
-    case 32: Launch<R, 32>::go(c); return true;
-    case 64: Launch<R, 64>::go(c); return true;
-    case 128: Launch<R, 128>::go(c); return true;
-    case 256: Launch<R, 256>::go(c); return true;
-    case 512:
-        if constexpr (sizeof(R) == 4) {
-            Launch<R, 512>::go(c);
-            return true;
-        }
+        PPPM_FFT_POW2(PPPM_CASE)
+        PPPM_FFT_MIXED_ONLY(PPPM_CASE_MIXED)
+    default:
         return false;
-    case 1024:
-        if constexpr (sizeof(R) == 4) {
-            Launch<R, 1024>::go(c);
-            return true;
-        }
-        return false;
-    default: return false;
     }
+#undef PPPM_CASE
+#undef PPPM_CASE_MIXED
+}
+
+bool fft_length_ok(int n, bool mixed)
+{
+#define PPPM_YES(n) \
+    case n:         \
+        return true;
+#define PPPM_IF_MIXED(n) \
+    case n:              \
+        return mixed;
+    switch (n) {
+        PPPM_FFT_POW2(PPPM_YES)
+        PPPM_FFT_MIXED_ONLY(PPPM_IF_MIXED)
+    default:
+        return false;
+    }
+#undef PPPM_YES
+#undef PPPM_IF_MIXED
 }
 
 template <typename R, int NC> struct XFwd {
@@ -819,8 +883,9 @@ hipError_t run_own_poisson(pppm_plan_s* pl, int mode, int slot, double* energy_o
 
 bool own_fft_supported(const int K[3], bool mixed)
 {
-    const int hi = mixed ? 1024 : 256;  // FP64: register stages of at most 16 values
-    return pow2_in(K[0], 8, hi) && pow2_in(K[1], 8, hi) && pow2_in(K[2], 8, hi);
+    // FP64 keeps to powers of two up to 256: register stages of at most 16 values
+    return K[0] >= 8 && K[0] % 2 == 0 && fft_length_ok(K[0] / 2, mixed) && K[1] >= 8 && fft_length_ok(K[1], mixed) &&
+           K[2] >= 8 && fft_length_ok(K[2], mixed);
 }
 
 // Launch shapes: about `target` complex values per block, fewer when that
@@ -831,20 +896,28 @@ void own_fft_shapes(pppm_plan_s* pl)
     const int nxh = Kx / 2 + 1, Nc = Kx / 2;
     const int target = pl->mixed ? 2048 : 1024;
     const int nrows = Ky * Kz;
-    int rows = target / Nc > 0 ? target / Nc : 1;
+    // batch sizes (rows, x columns) are powers of two
+    auto pow2_floor = [](int v) {
+        int p = 1;
+        while (2 * p <= v) p *= 2;
+        return p;
+    };
+    int rows = pow2_floor(target / Nc > 0 ? target / Nc : 1);
     while (rows > 1 && (nrows + rows - 1) / rows < 512) rows /= 2;
     pl->fx_rows = rows;
-    int xy = target / Ky > 0 ? target / Ky : 1;
+    int xy = pow2_floor(target / Ky > 0 ? target / Ky : 1);
     if (xy > 16) xy = 16;
     while (xy > 4 && Kz * ((nxh + xy - 1) / xy) < 512) xy /= 2;
     pl->fy_xc = xy;
-    int xz = target / Kz > 0 ? target / Kz : 1;
+    int xz = pow2_floor(target / Kz > 0 ? target / Kz : 1);
     if (xz > 16) xz = 16;
     while (xz > 4 && Ky * ((nxh + xz - 1) / xz) < 512) xz /= 2;
     pl->fz_xc = xz;
     pl->fz_blocks = Ky * ((nxh + xz - 1) / xz);
-    // x and y fused per plane: mixed form, 16 <= K_x / 2, K_y <= 512, plane within XY_MAX
-    pl->fft_xy = pl->mixed && Nc >= 16 && Ky >= 16 && Nc <= 512 && Ky <= 512 && Nc * Ky <= XY_MAX &&
+    // x and y fused per plane: mixed form, powers of two 16 <= K_x / 2, K_y <= 512,
+    // plane within XY_MAX
+    const bool p2 = (Nc & (Nc - 1)) == 0 && (Ky & (Ky - 1)) == 0;
+    pl->fft_xy = pl->mixed && p2 && Nc >= 16 && Ky >= 16 && Nc <= 512 && Ky <= 512 && Nc * Ky <= XY_MAX &&
                  xy_lds_bytes(Nc, Ky) + 1024 <= pl->lds_limit;
     const int per_line = 128 / (pl->mixed ? 8 : 16);
     pl->fft_pitch = (nxh + per_line - 1) / per_line * per_line;
@@ -854,10 +927,7 @@ void own_fft_shapes(pppm_plan_s* pl)
 // The z pass gives each thread at most one task between its transforms.
 bool own_fft_shapes_ok(const pppm_plan_s* pl)
 {
-    int lg = 0;
-    while ((1 << lg) < pl->geo.K[2]) ++lg;
-    const int n1 = 1 << ((lg + 1) / 2);
-    return n1 * pl->fz_xc <= FFT_THREADS;
+    return split_n1(pl->geo.K[2]) * pl->fz_xc <= FFT_THREADS;
 }
 
 size_t own_fft_lds_max(const pppm_plan_s* pl)
