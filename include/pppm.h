@@ -10,8 +10,10 @@
  *      coefficients onto a periodic mesh;
  *   3. Poisson solve in k-space by FFT (Equation 2; Section 3.2): the
  *      library's own transform kernels when every mesh size is a power of
- *      two (8..1024 in the mixed form, 8..256 in FP64), rocFFT otherwise,
- *      with the influence-function multiply and energy sums in between;
+ *      two (8..1024 in the mixed form, 8..256 in FP64) or, in the mixed
+ *      form, 2^a m with m in {3, 5, 7, 9} up to 448 (K_x / 2 from the same
+ *      list), rocFFT otherwise, with the influence-function multiply and
+ *      energy sums in between;
  *   4. fieldforce (the paper's Distribute-Force): gather the three field
  *      meshes (ik) or the derivative-weighted potential (ad) back to forces
  *      F_j = -q_j grad Phi (Equation 3).
