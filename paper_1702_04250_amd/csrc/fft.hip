@@ -177,12 +177,6 @@ template <int N> struct Split {
     static constexpr int N2 = N / N1;
 };
 
-// Transforms M sequences of length N (M a power of two).  ld(n, m) gives
-// element n of sequence m, st(k, m, v) takes coefficient k; ex is an LDS
-// buffer of N * M values; tw the LDS twiddle table with W_N^i at
-// tw[i * tstride].  Every thread of the block must call it; it ends with a
-// barrier.  Tasks map m fastest so that the lanes of a wavefront touch
-// consecutive sequences.
 // Stage A of one task: v[j] holds element t + N2 j of sequence m; its
 // length-N1 transform times W_N^(t k1) goes to ex.
 template <int N1, int N2, bool INV, typename R>
@@ -209,6 +203,12 @@ __device__ __forceinline__ void stage_b(Cplx<R>* v, int k1, int m, int lm, const
     Dft<N2, INV, R>::run(v);
 }
 
+// Transforms M sequences of length N (M a power of two).  ld(n, m) gives
+// element n of sequence m, st(k, m, v) takes coefficient k; ex is an LDS
+// buffer of N * M values; tw the LDS twiddle table with W_N^i at
+// tw[i * tstride].  Every thread of the block must call it; it ends with a
+// barrier.  Tasks map m fastest so that the lanes of a wavefront touch
+// consecutive sequences.
 template <int N, bool INV, typename R, typename Ld, typename St>
 __device__ __forceinline__ void fft2(int M, Ld ld, St st, Cplx<R>* ex, const Cplx<R>* tw, int tstride)
 {
