@@ -269,20 +269,31 @@ int split_edge(int K, int b, int P)
 }
 
 // Default tile: the first usable shape of a preference list, each axis split
-// evenly.  On the 128^3 mesh of the benchmark (P = 5, mixed precision) a
-// 32 x 16 x 8 tile gave the lowest make_rho + ad gather time and 32 x 8 x 8
-// the lowest make_rho + ik gather time (the ik gather stages three meshes).
+// evenly.  Measured (mixed precision, whole step: particle map + make_rho +
+// Poisson + fieldforce): ad keeps 32 x 16 x 8 (on the 524,288-charge 128^3
+// system 32 x 8 x 16 was within noise of it at P = 5 and on the 4.2M-charge
+// 256^3 system at P = 7 slower, 1.47 against 1.39 ms); ik takes 32 x 16 x 8
+// with the full LDS (161 against 167 us at P = 5 on 128^3, 2.03 against
+// 2.29 ms at P = 7 on 256^3, where the tiles that keep the gather's three
+// staged meshes within 79 KiB of LDS were 32 x 8 x 8 and 16 x 8 x 8).
+// Tiles stay at 4,096 points: the mixed form's fixed-point exponent is set
+// per tile from the charges it reads, so a larger tile sums more coarsely
+// (32 x 16 x 16 at P = 7 was faster still, but put the 4.2M-charge mesh
+// charge past 1e-4).
 std::string default_tile(pppm_plan_s* pl)
 {
     static const int prefs_ad[][3] = {{32, 16, 8}, {32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
-    static const int prefs_ik[][3] = {{32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
+    static const int prefs_ik[][3] = {{32, 16, 8}, {32, 8, 16}, {32, 8, 8}, {16, 16, 8},
+                                      {16, 8, 8},  {8, 8, 8},   {8, 8, 4},  {4, 4, 4}};
     const bool ik = pl->p.diff == PPPM_DIFF_IK;
     const int (*prefs)[3] = ik ? prefs_ik : prefs_ad;
-    const int nprefs = ik ? 6 : 7;
+    const int nprefs = ik ? 8 : 7;
     std::string why;
-    // first within the LDS size that keeps several workgroups per CU, then
-    // anything the device holds (small meshes that cannot be split)
-    for (size_t budget : {LDS_PREFERRED, pl->lds_limit}) {
+    // first within the LDS size that keeps several workgroups per CU (the
+    // mixed ik gather: anything the device holds, its best tiles need more),
+    // then anything the device holds (small meshes that cannot be split)
+    const size_t first = (ik && pl->mixed) ? pl->lds_limit : LDS_PREFERRED;
+    for (size_t budget : {first, pl->lds_limit}) {
         for (int k = 0; k < nprefs; ++k) {
             const int* pref = prefs[k];
             int B[3];
