@@ -142,3 +142,30 @@ def test_stale_forward_is_rejected(c4):
         e1.backward()
     plan.sync()
     plan.close()
+
+
+@pytest.mark.parametrize("mesh", [(48, 40, 36), (32, 64, 16)])
+def test_ik_backward_on_meshes_of_the_library_transforms(mesh):
+    # the ik adjoint needs the potential, which ik plans compute on demand
+    # (a potential-only z pass and the inverse passes); mixed-radix and
+    # power-of-two meshes, mixed precision, against the oracle's adjoint
+    lo = (0.0, 0.0, 0.0)
+    length = (mesh[0] * 1.05, mesh[1] * 0.95, mesh[2] * 1.1)
+    pos, q = W.random_system(600, length, seed=mesh[0] + mesh[2])
+    q = q - q.mean()
+    print(f"case ik backward mesh={mesh}", flush=True)
+    plan = make_plan(pkg, lo, length, mesh, 5, 0.5, 1.0, "ik", "mixed", torch.float32, len(q))
+    pos_r, q_r = io_round(pos, q, torch.float32)
+    tp = torch.tensor(pos_r, dtype=torch.float32, device=DEV, requires_grad=True)
+    tq = torch.tensor(q_r, dtype=torch.float32, device=DEV, requires_grad=True)
+    e = pkg.pppm_energy(tp, tq, plan)
+    e.backward()
+    torch.cuda.synchronize()
+    plan.sync()
+    gp = tp.grad.cpu().numpy().astype(np.float64)
+    gq = tq.grad.cpu().numpy().astype(np.float64)
+    plan.close()
+    ref = oracle.energy_gradients(pos_r, q_r, lo, length, mesh, 5, 0.5, 1.0, "ik")
+    ep, eq = rms_rel(gp, ref["grad_pos"]), rms_rel(gq, ref["grad_q"])
+    print(f"  grad_pos {ep:.3e} grad_q {eq:.3e}", flush=True)
+    assert ep <= TOL_ORACLE["mixed"] and eq <= TOL_ORACLE["mixed"]
