@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--shift-work", action="store_true",
                     help="for each order P = 3..7, the coarsest mesh meeting a force-error target on the "
                          "benchmark system, and the step time there; prints a table and exits")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print the per-dispatch mean of every counter in a rocprofv3 --pmc output folder")
     ap.add_argument("--summarize", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR "
                          "(subfolders trace, fetch, write, calib_fetch, calib_write) and exit")
@@ -137,6 +139,34 @@ def summarize(folder):
             continue
         tot = f * 1024.0 * cal["FETCH_SIZE"] + w * 1024.0 * cal["WRITE_SIZE"]
         out.append(f"| {k} | {f:.1f} | {w:.1f} | traffic[{k}] = {tot:.0f} |")
+    return "\n".join(out)
+
+
+def summarize_counters(folder):
+    """Markdown table: per kernel of the step, the mean over its dispatches of
+    each counter (summed over the counter's instances within a dispatch)."""
+    per = {}
+    names = []
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        k, c = _short(r.get("Kernel_Name", "")), r.get("Counter_Name")
+        if not k.startswith("k_") or k in ("k_influence", "k_fft_twiddles"):
+            continue
+        if c not in names:
+            names.append(c)
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = per.setdefault(k, {}).setdefault(c, {})
+        d[key] = d.get(key, 0.0) + float(r["Counter_Value"])
+    ratio = "SQ_LDS_BANK_CONFLICT" in names and "SQ_LDS_IDX_ACTIVE" in names
+    head = names + (["conflict / LDS active"] if ratio else [])
+    out = [f"source hash: {source_hash()}", "", "| kernel | " + " | ".join(head) + " |",
+           "|---|" + "---|" * len(head)]
+    for k, cs in per.items():
+        mean = {c: sum(v.values()) / len(v) for c, v in cs.items() if v}
+        vals = [f"{mean[c]:.0f}" if c in mean else "" for c in names]
+        if ratio:
+            act = mean.get("SQ_LDS_IDX_ACTIVE", 0.0)
+            vals.append(f"{mean.get('SQ_LDS_BANK_CONFLICT', 0.0) / act:.2f}" if act else "")
+        out.append(f"| {k} | " + " | ".join(vals) + " |")
     return "\n".join(out)
 
 
@@ -432,6 +462,9 @@ def shift_work(torch, pkg, workloads, steps, warmup):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters))
+        return
     if args.summarize:
         print(summarize(args.summarize))
         return

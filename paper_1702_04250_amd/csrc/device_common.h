@@ -27,6 +27,16 @@ __device__ __forceinline__ int xcd_remap(int wg, int nwg)
     return (local / CHUNK) * ROUND + x * CHUNK + local % CHUNK;
 }
 
+// Deals the workgroups to the XCDs in NUM_XCD contiguous runs: XCD x takes
+// logical workgroups [x * per, (x + 1) * per), per = nwg / NUM_XCD.  The
+// tail that does not fill a run keeps the identity order.
+__device__ __forceinline__ int xcd_contiguous(int wg, int nwg)
+{
+    const int per = nwg / NUM_XCD;
+    if (wg >= per * NUM_XCD) return wg;
+    return (wg % NUM_XCD) * per + wg / NUM_XCD;
+}
+
 // Record of a binned particle: stencil start within its tile plus the
 // fraction (t in [0, B]) per axis, and the charge.
 template <typename R> struct Rec;

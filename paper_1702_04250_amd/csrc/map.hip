@@ -400,7 +400,10 @@ __global__ __launch_bounds__(MAP_THREADS) void k_scatter(int n, const TI* __rest
 // histogram chunk scans the bin totals itself (a few KiB, read from L2)
 // into LDS and scatters its chunk with them; block 0 also publishes
 // offsets[0 .. nbins] and the statistics, as the single-block scan would.
-// This saves that kernel's launch.
+// This saves that kernel's launch.  Consecutive chunks write adjacent
+// records of every bin, so each XCD takes one contiguous run of chunks:
+// a record line is then filled within one L2 instead of being written back
+// in parts from several.
 constexpr int FUSED_SCAN_MAX_BINS = 8192;
 
 template <typename TI, typename R>
@@ -466,8 +469,9 @@ __global__ __launch_bounds__(HIST_THREADS) void k_scatter_scan(int n, int chunk,
         }
     }
     __syncthreads();
-    const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-    const int* __restrict__ row = hist + (size_t)blockIdx.x * nbins;
+    const int cb = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int i0 = cb * chunk, i1 = min(n, i0 + chunk);
+    const int* __restrict__ row = hist + (size_t)cb * nbins;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += HIST_THREADS)
         scatter_charge<TI, R>(
             i, pos, q, g, [&](int bin) { return loff[bin] + row[bin] + slot[i]; }, rec, perm);
