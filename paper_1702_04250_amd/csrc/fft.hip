@@ -14,7 +14,7 @@
 //   4. y, inverse, per output mesh, in place.
 //   5. x, inverse: each row's K_x / 2 + 1 coefficients are folded into
 //      K_x / 2 complex values, transformed back and unpacked into K_x reals;
-//      one block of this pass also takes the final FP64 energy sums.
+//      one extra block of this pass takes the final FP64 energy sums.
 // In the mixed form, planes of at most XY_MAX complex values run passes 1+2
 // and 4+5 fused, one z plane per block (k_fft_xy_fwd, k_fft_yx_inv).
 //
@@ -473,6 +473,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
                                                            long long out_stride, const Cplx<R>* __restrict__ twg,
                                                            EnergySums es, int final_sums)
 {
+    // one extra column of blocks: its first block takes the final energy
+    // sums (the z pass that wrote the k-space partials has completed) on a
+    // CU of its own, beside the transform blocks
+    if (final_sums && blockIdx.x == gridDim.x - 1) {
+        if (blockIdx.y == 0) energy_final_block(es);
+        return;
+    }
     using C = Cplx<R>;
     constexpr int Kx = 2 * NC, nxh = NC + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -511,8 +518,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
         const int m = i / NC, n = i - m * NC;
         dst[i] = s[n * P + m];
     }
-    // the z pass, which took the k-space partial sums, has completed
-    if (final_sums && blockIdx.x == 0 && blockIdx.y == 0) energy_final_block(es);
 }
 
 // Passes 1 and 2 fused (mixed form, planes that fit in LDS): one z plane per
@@ -521,32 +526,72 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
 // transform then runs on K_x / 2 columns, and the two real columns are
 // separated afterwards by the symmetry of the transform of a real sequence,
 //   Y_0(k) = (Q(k) + conj Q(-k)) / 2,   Y_{K_x/2}(k) = (Q(k) - conj Q(-k)) / 2i.
+//
+// HALF: two blocks per plane, one for the even and one for the odd y
+// coefficients (radix-2 split of the y transform by output index).  With
+// H = K_y / 2 and rows r_m of the plane,
+//   Y(2j)   = sum_{m<H} (r_m + r_{m+H}) W_H^{jm},
+//   Y(2j+1) = sum_{m<H} (r_m - r_{m+H}) W_{K_y}^m W_H^{jm},
+// and the x transform is linear, so each block sums or subtracts the row
+// pairs as it loads them and transforms H rows and H-point columns.  Every
+// block reads the whole plane; the pass then has twice as many blocks,
+// which a mesh of fewer planes than twice the CU count needs to fill the
+// chip.  In the odd half the partner of coefficient j in the symmetry above
+// is H - 1 - j (index -(2j+1) = 2(H-1-j)+1 mod K_y), in the even half
+// (H - j) mod H.
 constexpr int XY_THREADS = 1024;
+constexpr int XY_HALF_THREADS = 512;
 
-template <typename R, int NC, int KY>
-__global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__ in, Cplx<R>* __restrict__ out, int nxp,
-                                                           const Cplx<R>* __restrict__ twg)
+// Block b of a split pass over nb = 2 * planes blocks: blocks b and b + 8
+// take the two halves of one plane, so both run on one XCD and its L2
+// serves the second read of the plane.
+__device__ __forceinline__ void plane_half(int b, int nb, int& plane, int& h)
+{
+    if (nb % (2 * NUM_XCD) == 0) {
+        plane = (b / (2 * NUM_XCD)) * NUM_XCD + b % NUM_XCD;
+        h = (b / NUM_XCD) & 1;
+    } else {
+        plane = b >> 1;
+        h = b & 1;
+    }
+}
+
+template <typename R, int NC, int KY, bool HALF>
+__global__ __launch_bounds__(HALF ? XY_HALF_THREADS : XY_THREADS) void k_fft_xy_fwd(const R* __restrict__ in,
+                                                                                    Cplx<R>* __restrict__ out,
+                                                                                    int nxp,
+                                                                                    const Cplx<R>* __restrict__ twg)
 {
     using C = Cplx<R>;
-    constexpr int Kx = 2 * NC, P = KY + 1;
+    constexpr int Kx = 2 * NC, KR = HALF ? KY / 2 : KY, P = KR + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* twx = (C*)smem_raw;
     C* twy = twx + Kx;
     C* s = twy + KY;      // [NC][P]: rows transposed, then the y exchange buffer
-    C* q = s + NC * P;    // [NC * KY]: the x exchange buffer, then the plane [y][k]
+    C* q = s + NC * P;    // [NC * KR]: the x exchange buffer, then the plane [y][k]
     load_table(twx, twg, Kx + KY);  // the x and y tables are adjacent
-    const C* src = (const C*)(in + (size_t)blockIdx.x * KY * Kx);
+    int plane = blockIdx.x, h = 0;
+    if constexpr (HALF) plane_half(blockIdx.x, gridDim.x, plane, h);
+    const C* src = (const C*)(in + (size_t)plane * KY * Kx);
     staged_copy<C>(
-        KY * NC, [&](int i) { return src[i]; },
+        KR * NC,
+        [&](int i) {
+            C v = src[i];
+            if constexpr (HALF) {
+                const C w = src[i + KR * NC];  // row m + K_y / 2
+                v = h ? C{v.x - w.x, v.y - w.y} : C{v.x + w.x, v.y + w.y};
+            }
+            return v;
+        },
         [&](int i, C v) {
             const int m = i / NC, n = i - m * NC;
             s[n * P + m] = v;
         });
     __syncthreads();
     fft2<NC, false, R>(
-        KY, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
+        KR, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
     // split into the half spectrum of each row; column 0 carries X_0 + i X_NC
-    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < KR * NC; i += blockDim.x) {
         const int m = i / NC, k = i - m * NC;
         const C za = s[k * P + m];
         const C zb = s[(k == 0 ? 0 : NC - k) * P + m];
@@ -560,23 +605,27 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__
             const C wf = cmul(twx[k], fo);
             x = C{fe.x + wf.x, fe.y + wf.y};
         }
+        if (HALF && h) x = cmul(x, twy[m]);  // W_{K_y}^m
         q[m * NC + k] = x;
     }
     __syncthreads();
-    fft2<KY, false, R>(
-        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy, 1);
-    C* dst = out + (size_t)blockIdx.x * KY * nxp;
-    for (int i = threadIdx.x; i < KY * (NC + 1); i += blockDim.x) {
-        const int ky = i / (NC + 1), k = i - ky * (NC + 1);
+    fft2<KR, false, R>(
+        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy,
+        HALF ? 2 : 1);
+    C* dst = out + (size_t)plane * KY * nxp;
+    for (int i = threadIdx.x; i < KR * (NC + 1); i += blockDim.x) {
+        const int j = i / (NC + 1), k = i - j * (NC + 1);
         C v;
         if (k > 0 && k < NC) {
-            v = q[ky * NC + k];
+            v = q[j * NC + k];
         } else {
-            const C a = q[ky * NC];
-            const C b = q[((KY - ky) % KY) * NC];  // Q(-k), used conjugated
+            const int jp = (HALF && h) ? KR - 1 - j : (KR - j) % KR;
+            const C a = q[j * NC];
+            const C b = q[jp * NC];  // the partner, used conjugated
             v = (k == 0) ? C{R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)}
                          : C{R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
         }
+        const int ky = HALF ? 2 * j + h : j;
         dst[(size_t)ky * nxp + k] = v;
     }
 }
@@ -585,38 +634,67 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy_fwd(const R* __restrict__
 // x = 0 and x = K_x/2 columns are Hermitian in k_y, so their y transforms
 // are real: they go through one complex column Q = X_0 + i X_{K_x/2} and come
 // out as its real and imaginary parts.
-template <typename R, int NC, int KY>
-__global__ __launch_bounds__(XY_THREADS) void k_fft_yx_inv(const Cplx<R>* __restrict__ spec, R* __restrict__ out,
-                                                           int nxp, long long spec_stride, long long out_stride,
-                                                           const Cplx<R>* __restrict__ twg, EnergySums es,
-                                                           int final_sums)
+//
+// HALF: two blocks per plane, one for the even and one for the odd output
+// rows (radix-2 split of the inverse y transform by output index).  With
+// H = K_y / 2,
+//   x(2j)   = sum_{k<H} (X(k) + X(k+H)) W_H^{-jk},
+//   x(2j+1) = sum_{k<H} (X(k) - X(k+H)) W_{K_y}^{-k} W_H^{-jk};
+// the even and odd samples of the real columns x = 0 and x = K_x/2 are real
+// too, so the packed column goes through unchanged.
+template <typename R, int NC, int KY, bool HALF>
+__global__ __launch_bounds__(HALF ? XY_HALF_THREADS : XY_THREADS) void k_fft_yx_inv(
+    const Cplx<R>* __restrict__ spec, R* __restrict__ out, int nxp, long long spec_stride, long long out_stride,
+    const Cplx<R>* __restrict__ twg, EnergySums es, int final_sums)
 {
+    // one extra column of blocks: its first block takes the final energy sums
+    if (final_sums && blockIdx.x == gridDim.x - 1) {
+        if (blockIdx.y == 0) energy_final_block(es);
+        return;
+    }
     using C = Cplx<R>;
-    constexpr int Kx = 2 * NC, P = KY + 1;
+    constexpr int Kx = 2 * NC, KR = HALF ? KY / 2 : KY, P = KR + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* twx = (C*)smem_raw;
     C* twy = twx + Kx;
     C* s = twy + KY;    // [NC][P]: the y exchange buffer, then the rows transposed
-    C* q = s + NC * P;  // [KY][NC]: the plane, then the x exchange buffer
+    C* q = s + NC * P;  // [KR][NC]: the plane, then the x exchange buffer
     load_table(twx, twg, Kx + KY);
-    const C* src = spec + blockIdx.y * spec_stride + (size_t)blockIdx.x * KY * nxp;
+    int plane = blockIdx.x, h = 0;
+    if constexpr (HALF) plane_half(blockIdx.x, gridDim.x - (final_sums ? 1 : 0), plane, h);
+    const C* src = spec + blockIdx.y * spec_stride + (size_t)plane * KY * nxp;
+    // row ky of the plane, column 0 packed as X_0 + i X_NC
+    auto packed = [&](int ky, int k) {
+        C v = src[(size_t)ky * nxp + k];
+        if (k == 0) {
+            const C b = src[(size_t)ky * nxp + NC];
+            v = C{v.x - b.y, v.y + b.x};
+        }
+        return v;
+    };
     staged_copy<C>(
-        KY * NC,
+        KR * NC,
         [&](int i) {
             const int ky = i / NC, k = i - ky * NC;
-            C v = src[(size_t)ky * nxp + k];
-            if (k == 0) {
-                const C b = src[(size_t)ky * nxp + NC];
-                v = C{v.x - b.y, v.y + b.x};  // X_0 + i X_NC
+            C v = packed(ky, k);
+            if constexpr (HALF) {
+                const C w = packed(ky + KR, k);
+                if (h) {
+                    const C t = twg[Kx + ky];  // W_{K_y}^{ky}, used conjugated
+                    v = cmul(C{v.x - w.x, v.y - w.y}, C{t.x, -t.y});
+                } else {
+                    v = C{v.x + w.x, v.y + w.y};
+                }
             }
             return v;
         },
         [&](int i, C v) { q[i] = v; });
     __syncthreads();
-    fft2<KY, true, R>(
-        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy, 1);
+    fft2<KR, true, R>(
+        NC, [&](int n, int m) { return q[n * NC + m]; }, [&](int k, int m, C v) { q[k * NC + m] = v; }, s, twy,
+        HALF ? 2 : 1);
     // fold each row into NC complex values: Z'_k = (X_k + conj X_{NC-k}) + i W^-k (X_k - conj X_{NC-k})
-    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < KR * NC; i += blockDim.x) {
         const int m = i / NC, k = i - m * NC;  // k fastest: row reads of q are consecutive
         const C w0 = q[m * NC];  // x_0 + i x_NC, both real
         const C xa = (k == 0) ? C{w0.x, R(0)} : q[m * NC + k];
@@ -629,14 +707,13 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_yx_inv(const Cplx<R>* __rest
     }
     __syncthreads();
     fft2<NC, true, R>(
-        KY, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
-    C* dst = (C*)(out + blockIdx.y * out_stride + (size_t)blockIdx.x * KY * Kx);
-    for (int i = threadIdx.x; i < KY * NC; i += blockDim.x) {
+        KR, [&](int n, int m) { return s[n * P + m]; }, [&](int k, int m, C v) { s[k * P + m] = v; }, q, twx, 2);
+    C* dst = (C*)(out + blockIdx.y * out_stride + (size_t)plane * KY * Kx);
+    for (int i = threadIdx.x; i < KR * NC; i += blockDim.x) {
         const int m = i / NC, n = i - m * NC;
-        dst[i] = s[n * P + m];
+        const int y = HALF ? 2 * m + h : m;
+        dst[y * NC + n] = s[n * P + m];
     }
-    // the z pass, which took the k-space partial sums, has completed
-    if (final_sums && blockIdx.x == 0 && blockIdx.y == 0) energy_final_block(es);
 }
 
 // Twiddle tables of the three axes, tw_d[i] = exp(-2 pi i * i / K_d), in FP64
@@ -745,7 +822,8 @@ template <typename R, int NC> struct XInv {
         const int nrows = c.fg.K[1] * c.fg.K[2], rows = c.pl->fx_rows;
         const size_t lds =
             sizeof(Cplx<R>) * (2 * NC + (size_t)rows * (NC + 1) + (size_t)NC * (rows + 1) + (size_t)NC * rows);
-        k_fft_x_inv<R, NC><<<dim3((nrows + rows - 1) / rows, c.nout), FFT_THREADS, lds, c.pl->stream>>>(
+        k_fft_x_inv<R, NC><<<dim3((nrows + rows - 1) / rows + c.final_sums, c.nout), FFT_THREADS, lds,
+                             c.pl->stream>>>(
             (const Cplx<R>*)c.spec, (R*)c.field, c.fg.nxp, nrows, rows, c.fg.slot, c.pl->ncell, (const Cplx<R>*)c.tw,
             c.es, c.final_sums);
     }
@@ -798,20 +876,38 @@ template <typename R, int KZ> struct ZSolve {
 // buffers stay within the LDS of one block).
 constexpr int XY_MAX = 8192;
 
-size_t xy_lds_bytes(int nc, int ky) { return sizeof(Cplx<float>) * (2 * nc + ky + (size_t)nc * (ky + 1) + (size_t)nc * ky); }
+// LDS of a fused pass transforming kr rows of a plane (kr = K_y, or K_y / 2
+// when the plane is split over two blocks).
+size_t xy_lds_bytes(int nc, int ky, int kr)
+{
+    return sizeof(Cplx<float>) * (2 * nc + ky + (size_t)nc * (kr + 1) + (size_t)nc * kr);
+}
+
+// A pass whose blocks (one per plane and output) would leave CUs idle or
+// one block each runs split, two blocks per plane.
+constexpr int XY_SPLIT_BELOW = 512;
+
+template <int NC, int KY, bool HALF> void xy_run(const Ctx& c, bool inverse)
+{
+    const size_t lds = xy_lds_bytes(NC, KY, HALF ? KY / 2 : KY);
+    const int threads = HALF ? XY_HALF_THREADS : XY_THREADS;
+    const int nb = HALF ? 2 * c.fg.K[2] : c.fg.K[2];
+    const Cplx<float>* tw = (const Cplx<float>*)c.tw;
+    if (!inverse)
+        k_fft_xy_fwd<float, NC, KY, HALF><<<nb, threads, lds, c.pl->stream>>>((const float*)c.pl->rho,
+                                                                             (Cplx<float>*)c.A, c.fg.nxp, tw);
+    else
+        k_fft_yx_inv<float, NC, KY, HALF><<<dim3(nb + c.final_sums, c.nout), threads, lds, c.pl->stream>>>(
+            (const Cplx<float>*)c.spec, (float*)c.field, c.fg.nxp, c.fg.slot, c.pl->ncell, tw, c.es, c.final_sums);
+}
 
 template <int NC, int KY> void xy_go(const Ctx& c, bool inverse)
 {
     if constexpr (NC * KY <= XY_MAX) {
-        const size_t lds = xy_lds_bytes(NC, KY);
-        const Cplx<float>* tw = (const Cplx<float>*)c.tw;
-        if (!inverse)
-            k_fft_xy_fwd<float, NC, KY><<<c.fg.K[2], XY_THREADS, lds, c.pl->stream>>>(
-                (const float*)c.pl->rho, (Cplx<float>*)c.A, c.fg.nxp, tw);
+        if (c.fg.K[2] * (inverse ? c.nout : 1) < XY_SPLIT_BELOW)
+            xy_run<NC, KY, true>(c, inverse);
         else
-            k_fft_yx_inv<float, NC, KY><<<dim3(c.fg.K[2], c.nout), XY_THREADS, lds, c.pl->stream>>>(
-                (const Cplx<float>*)c.spec, (float*)c.field, c.fg.nxp, c.fg.slot, c.pl->ncell, tw, c.es,
-                c.final_sums);
+            xy_run<NC, KY, false>(c, inverse);
     }
 }
 
@@ -918,7 +1014,7 @@ void own_fft_shapes(pppm_plan_s* pl)
     // plane within XY_MAX
     const bool p2 = (Nc & (Nc - 1)) == 0 && (Ky & (Ky - 1)) == 0;
     pl->fft_xy = pl->mixed && p2 && Nc >= 16 && Ky >= 16 && Nc <= 512 && Ky <= 512 && Nc * Ky <= XY_MAX &&
-                 xy_lds_bytes(Nc, Ky) + 1024 <= pl->lds_limit;
+                 xy_lds_bytes(Nc, Ky, Ky) + 1024 <= pl->lds_limit;
     const int per_line = 128 / (pl->mixed ? 8 : 16);
     pl->fft_pitch = (nxh + per_line - 1) / per_line * per_line;
     pl->spec_len = (int64_t)Kz * Ky * pl->fft_pitch;
