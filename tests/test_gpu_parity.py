@@ -75,14 +75,16 @@ EDGE_BOX = ((-3.0, 2.0, 0.5), (11.0, 13.0, 7.5))
 
 
 @pytest.mark.parametrize("mesh", [(8, 16, 32), (32, 8, 16), (16, 64, 8), (128, 16, 8), (32, 32, 16), (256, 32, 8),
-                                  (48, 40, 36), (20, 28, 72), (112, 12, 18), (36, 56, 24), (160, 10, 14)])
+                                  (48, 40, 36), (20, 28, 72), (112, 12, 18), (36, 56, 24), (160, 10, 14),
+                                  (32, 32, 12), (64, 32, 20)])
 @pytest.mark.parametrize("diff", ["ad", "ik"])
 @pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
 def test_meshes_with_own_transforms(mesh, diff, prec, io):
     # meshes whose sizes are powers of two, or in the mixed form 2^a m with m
     # in {3, 5, 7, 9}, take the library's own transforms (other sizes take
     # rocFFT): anisotropic shapes, smallest axes, radix 3, 5, 7 and 9 stages,
-    # planes with and without the fused x-y passes
+    # planes with and without the fused x-y passes, fused passes split over
+    # two blocks per plane with the plane count a multiple of 8 and not
     lo = (-3.0, 1.0, 2.0)
     length = (mesh[0] * 0.9, mesh[1] * 1.1, mesh[2] * 1.0)
     pos, q = W.random_system(700, length, seed=mesh[0] * 7 + mesh[1], box_lo=lo)
