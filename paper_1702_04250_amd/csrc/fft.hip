@@ -883,8 +883,8 @@ size_t xy_lds_bytes(int nc, int ky, int kr)
     return sizeof(Cplx<float>) * (2 * nc + ky + (size_t)nc * (kr + 1) + (size_t)nc * kr);
 }
 
-// A pass whose blocks (one per plane and output) would leave CUs idle or
-// one block each runs split, two blocks per plane.
+// A pass with fewer blocks (one per plane and output mesh) than two per CU
+// of the chip runs split, two blocks per plane.
 constexpr int XY_SPLIT_BELOW = 512;
 
 template <int NC, int KY, bool HALF> void xy_run(const Ctx& c, bool inverse)
