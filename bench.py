@@ -185,14 +185,32 @@ def recorded_traffic(kernel):
     return float(m.group(1)) if m else None
 
 
-def algorithmic_bytes(kind, n, cells, prec):
+def recorded_avg_us(kernel):
+    """Average duration of `kernel` in the committed kernel-trace summary, or
+    None when the summary is missing or was taken on other sources."""
+    import re
+
+    if not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m = re.search(r"source hash: (\w+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(r"^\| " + kernel + r" \| \d+ \| ([0-9.]+) \|", text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def algorithmic_bytes(kind, n, cells, prec, rho_out=False):
     """Bytes the method must move per launch: particle records once, the mesh
-    once (written by make_rho, read by a gather), forces once."""
+    once (written by make_rho, read by a gather), forces once.  make_rho
+    writes the plan's transform input (FP32 in the mixed form, FP64 in the
+    FP64 form) and, only when the caller asks for it (rho_out), the FP64
+    mesh charge as well."""
     rec = 16 if prec == "mixed" else 32
     fmesh = 4 if prec == "mixed" else 8
     fout = 12 if prec == "mixed" else 24
     if kind == "make_rho":
-        return n * rec + cells * 8
+        return n * rec + cells * fmesh + (cells * 8 if rho_out and prec == "mixed" else 0)
     if kind == "fieldforce_ad":
         return n * (rec + fout) + cells * fmesh
     if kind == "fieldforce_ik":
@@ -369,39 +387,85 @@ def run_loop(torch, plan, pos, q, steps, warmup, diff, backward=False, flush=Non
     return res, forces, energy
 
 
-def cpu_baseline(w, order, pos_r, q_r, budget_s=12.0):
-    """The FP64 oracle's forward step (make_rho, Poisson, ad gather) on the host."""
+def kernel_loop_us(torch, stream, fn, reps=30):
+    """Average duration of one call of fn, from `reps` back-to-back calls
+    between one pair of HIP events on the plan's stream (no events between
+    the calls, so the figure is the kernels' own time)."""
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+    b.synchronize()
+    return 1e3 * a.elapsed_time(b) / reps
+
+
+def cpu_baseline(w, order, pos_r, q_r, phi, reps=3):
+    """The FP64 oracle's make_rho and ad fieldforce on the host, timed
+    separately (the Poisson step excluded, as on the GPU side of the metric),
+    on all the host threads this process may use and on one.  Several threads
+    follow the paper's "rethread" scheme: each thread spreads its share of
+    the charges into a private mesh (the oracle's own make_rho on that share),
+    the meshes are summed, and the gather splits the charges the same way.
+    The oracle runs unchanged; ctypes releases the interpreter lock while its
+    C loops run, so the threads run in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from oracle import oracle
 
     box = oracle.Box(w.box_lo, w.box_len, w.mesh, order)
-    G = oracle.influence_function(box, w.g_ewald, "ad")  # setup, untimed
-    times, res = [], None
-    t_start = time.perf_counter()
-    while not times or (time.perf_counter() - t_start < budget_s and len(times) < 5):
-        t0 = time.perf_counter()
-        res = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", G=G)
-        times.append(time.perf_counter() - t0)
-    t = statistics.median(times)
+    ncores = min(len(os.sched_getaffinity(0)), 16)
+    out = {}
+    for nt in sorted({ncores, 1}, reverse=True):
+        parts = np.array_split(np.arange(w.n), nt)
+        shares = [(np.ascontiguousarray(pos_r[p]), np.ascontiguousarray(q_r[p])) for p in parts]
+        t_rho, t_ff = [], []
+        with ThreadPoolExecutor(max_workers=nt) as ex:
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                meshes = list(ex.map(lambda sh: oracle.make_rho(sh[0], sh[1], box), shares))
+                rho = meshes[0] if nt == 1 else np.add.reduce(meshes)
+                t1 = time.perf_counter()
+                forces = list(ex.map(lambda sh: oracle.fieldforce_ad(sh[0], sh[1], box, phi)[0], shares))
+                t2 = time.perf_counter()
+                t_rho.append(t1 - t0)
+                t_ff.append(t2 - t1)
+        del rho, forces, meshes
+        tr, tf = statistics.median(t_rho), statistics.median(t_ff)
+        out[nt] = {"threads": nt, "make_rho_s": tr, "fieldforce_s": tf, "particles_per_s": w.n / (tr + tf)}
+    best = out[ncores]
     return {
-        "value": w.n / t,
+        "value": best["particles_per_s"],
         "unit": "particles/s",
-        "cores": 1,
+        "cores": ncores,
         "kind": "oracle",
-        "sample": (f"full workload ({w.n} charges, mesh {w.mesh[0]}^3, P={order}, ad), "
-                   f"make_rho + numpy-FFT Poisson + ad gather, median of {len(times)} runs, "
-                   "single-threaded C loops and pocketfft; influence function precomputed"),
-        "seconds_per_step": t,
-    }, res
+        "sample": (f"full workload ({w.n} charges, mesh {w.mesh[0]}^3, P={order}, ad): the FP64 oracle's make_rho "
+                   f"and ad fieldforce (C loops), Poisson excluded, median of {reps} runs each; {ncores} threads "
+                   "with private meshes per thread summed after the spread, and 1 thread"),
+        "make_rho_s": best["make_rho_s"],
+        "fieldforce_s": best["fieldforce_s"],
+        "one_thread": out[1],
+    }
 
 
-def shift_work(torch, pkg, workloads, steps, warmup):
+SHIFT_SIZES = [32, 40, 48, 56, 64, 72, 80, 96, 112, 128, 144, 160, 192, 224, 256]
+
+
+def shift_work(torch, pkg, workloads, steps, warmup, sizes=SHIFT_SIZES, targets=(1e-3, 1e-4), verbose=True):
     """Higher order on a coarser mesh (the paper's trade, its Section 2.3 and
     the results of Section 4): for each P, the meshes (of a list of FFT
     friendly sizes) whose mixed-form ad forces are within the target RMS
     relative error of a converged reference, and the fastest GPU step among
-    them (power-of-two meshes run the library's own transforms, the others
-    rocFFT, so the smallest mesh is not always the fastest).
-    Reference: the FP64 form at P = 7 on a 288^3 mesh (h = 0.59 A)."""
+    them, from the smallest such mesh up to the next power of two (power-of-
+    two meshes run the library's own transforms, most others rocFFT, so the
+    smallest mesh is not always the fastest).
+    Reference: the FP64 form of the same GPU path at P = 7 on a 288^3 mesh
+    (h = 0.59 A, g = 0.30); Ewald sums over 524,288 charges are out of reach,
+    and the oracle tests pin this setting's force error against exact Ewald
+    forces on a smaller system of the same density, h and g (below 1e-6)."""
     w = workloads.config(3)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
@@ -421,42 +485,54 @@ def shift_work(torch, pkg, workloads, steps, warmup):
     ref_plan, ref = forces(7, 288, "fp64", pos64, q64)
     ref_plan.close()
     den = float((ref ** 2).sum())
-    sizes = [32, 40, 48, 56, 64, 72, 80, 96, 112, 128, 144, 160, 192, 224, 256]
     # bring the clocks up before the first timed loop
     warm, _ = forces(5, 128, "mixed", pos, q)
     run_loop(torch, warm, pos, q, steps, warmup, "ad")
     warm.close()
+    errors, timed = {}, {}
+
+    def error_of(P, K):
+        if (P, K) not in errors:
+            plan, f = forces(P, K, "mixed", pos, q)
+            plan.close()
+            errors[(P, K)] = float(np.sqrt(((f - ref) ** 2).sum() / den))
+        return errors[(P, K)]
+
+    def step_of(P, K):
+        if (P, K) not in timed:
+            plan = pkg.Plan(w.box_lo, w.box_len, (K,) * 3, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
+                            max_particles=w.n, device=dev, stream=stream)
+            res, _, _ = run_loop(torch, plan, pos, q, steps, warmup, "ad")
+            plan.close()
+            timed[(P, K)] = res
+        return timed[(P, K)]
+
     rows = []
-    for target in (1e-3, 1e-4):
+    for target in targets:
         for P in range(3, 8):
-            # every size from the smallest one that meets the target up to
-            # the next power of two (whose Poisson step takes the library's
-            # own transforms) is timed; the fastest is reported
             best, smallest = None, None
             for K in sizes:
                 if smallest is not None and K > smallest and (K & (K - 1)) != 0 and (smallest & (smallest - 1)) == 0:
                     break
-                plan, f = forces(P, K, "mixed", pos, q)
-                err = float(np.sqrt(((f - ref) ** 2).sum() / den))
-                if err <= target:
-                    res, _, _ = run_loop(torch, plan, pos, q, steps, warmup, "ad")
-                    row = {"target": target, "P": P, "K": K, "h_A": w.box_len[0] / K, "force_err": err,
-                           "step_us": 1e3 * res["ms_per_step"],
-                           "kernels_us": {k[:-3]: round(v, 2) for k, v in res.items()
-                                          if k.endswith("_us") and k != "step_us"}}
-                    if smallest is None:
-                        smallest = K
-                    if best is None or row["step_us"] < best["step_us"]:
-                        best = row
-                    plan.close()
-                    if (K & (K - 1)) == 0:
-                        break
+                err = error_of(P, K)
+                if err > target:
                     continue
-                plan.close()
+                res = step_of(P, K)
+                row = {"target": target, "P": P, "K": K, "h_A": w.box_len[0] / K, "force_err": err,
+                       "step_us": 1e3 * res["ms_per_step"],
+                       "kernels_us": {k[:-3]: round(v, 2) for k, v in res.items()
+                                      if k.endswith("_us") and k != "step_us"}}
+                if smallest is None:
+                    smallest = K
+                if best is None or row["step_us"] < best["step_us"]:
+                    best = row
+                if (K & (K - 1)) == 0:
+                    break
             if best is not None:
                 best["smallest_K_meeting_target"] = smallest
             rows.append(best or {"target": target, "P": P, "K": None})
-            print(json.dumps(rows[-1]), flush=True)
+            if verbose:
+                print(json.dumps(rows[-1]), flush=True)
     return rows
 
 
@@ -508,8 +584,9 @@ def main():
                        max_particles=n, device=dev, stream=stream)
     head, f_ad, e_ad = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad")
     plan_ad.sync()
+    k_ad = kernel_times(torch, plan_ad, f_ad)
 
-    t_rho, t_ff = head["make_rho_us"], head["fieldforce_us"]
+    t_rho, t_ff = k_ad["make_rho"], k_ad["fieldforce"]
     b_rho = algorithmic_bytes("make_rho", n, cells, "mixed")
     b_ff = algorithmic_bytes("fieldforce_ad", n, cells, "mixed")
     dom, t_dom, b_dom = ("make_rho", t_rho, b_rho) if t_rho >= t_ff else ("fieldforce_ad", t_ff, b_ff)
@@ -528,39 +605,59 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}-P{order}: {w.notes}", "n": n, "mesh": list(w.mesh), "order": order,
-                   "diff": "ad", "prec": "mixed (f32 stencils, LDS fixed-point sums, gathers and FFTs; f64 mesh flush and energy)",
+                   "diff": "ad", "prec": "mixed (f32 stencils with unbiased fixed-point LDS sums, f32 gathers "
+                                         "and FFTs; f64 energy)",
                    "io_dtype": "f32", "step": "particle_map + make_rho + poisson + fieldforce"},
         "roofline": {"bound": "hbm", "kernel": STEP_KERNEL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(STEP_KERNEL[dom]),
-                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom},
+                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom,
+                     "timing": "HIP events around back-to-back launches of the step on the plan's stream",
+                     "profile_avg_launch_us": recorded_avg_us(STEP_KERNEL[dom])},
         "kernels_us": {k[:-3]: v for k, v in head.items() if k.endswith("_us") and k != "wall_ms_per_step"},
+        "kernel_loop_us": k_ad,
         "step_us_p10_p50_p90": head["step_us_p10_p50_p90"],
         "make_rho_fieldforce": {
             "ad": {"us": t_rho + t_ff, "particles_per_s": n / ((t_rho + t_ff) * 1e-6),
                    "hbm_frac": (b_rho + b_ff) / ((t_rho + t_ff) * 1e-6) / 1e9 / HBM_PEAK_GBS},
         },
     }
+    gpu_res = {}
     if not args.no_extras:
         plan_ik = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ik", "mixed", torch.float32,
                            max_particles=n, device=dev, stream=stream)
         ik, f_ik, _ = run_loop(torch, plan_ik, pos, q, args.steps, args.warmup, "ik")
+        k_ik = kernel_times(torch, plan_ik, f_ik)
         b_ffik = algorithmic_bytes("fieldforce_ik", n, cells, "mixed")
+        t_ik = k_ik["make_rho"] + k_ik["fieldforce"]
         out["make_rho_fieldforce"]["ik"] = {
-            "us": ik["make_rho_us"] + ik["fieldforce_us"],
-            "particles_per_s": n / ((ik["make_rho_us"] + ik["fieldforce_us"]) * 1e-6),
-            "hbm_frac": (b_rho + b_ffik) / ((ik["make_rho_us"] + ik["fieldforce_us"]) * 1e-6) / 1e9 / HBM_PEAK_GBS,
-            "ms_per_step": ik["ms_per_step"], "kernels_us": {k[:-3]: v for k, v in ik.items() if k.endswith("_us")},
+            "us": t_ik, "particles_per_s": n / (t_ik * 1e-6),
+            "hbm_frac": (b_rho + b_ffik) / (t_ik * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "ms_per_step": ik["ms_per_step"], "kernel_loop_us": k_ik,
+            "kernels_us": {k[:-3]: v for k, v in ik.items() if k.endswith("_us")},
         }
+        gpu_res["ik_forces"] = f_ik.cpu().numpy().astype(np.float64)
         plan_ik.close()
         # plain FP64 form on the same GPU (FP64 particle arrays of the same values)
         pos64, q64 = pos.double(), q.double()
         plan_64 = pkg.Plan(w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad", "fp64", torch.float64,
                            max_particles=n, device=dev, stream=stream)
         r64, f_64, e_64 = run_loop(torch, plan_64, pos64, q64, args.steps, args.warmup, "ad")
+        k_64 = kernel_times(torch, plan_64, f_64)
         out["fp64_form"] = {"ms_per_step": r64["ms_per_step"], "particles_per_s": n / (r64["ms_per_step"] * 1e-3),
                             "kernels_us": {k[:-3]: v for k, v in r64.items() if k.endswith("_us")},
+                            "kernel_loop_us": k_64,
                             "make_rho_fieldforce_particles_per_s":
-                                n / ((r64["make_rho_us"] + r64["fieldforce_us"]) * 1e-6)}
+                                n / ((k_64["make_rho"] + k_64["fieldforce"]) * 1e-6)}
+        # the mesh charge, forces and energy of each form, for the errors below
+        with torch.cuda.stream(stream):
+            rm = plan_ad.compute(pos, q, want_rho=True)
+            r6 = plan_64.compute(pos64, q64, want_rho=True)
+        plan_ad.sync()
+        plan_64.sync()
+        gpu_res.update(mixed=(rm["rho"].cpu().numpy(), rm["forces"].cpu().numpy().astype(np.float64),
+                              float(rm["energy"].cpu())),
+                       fp64=(r6["rho"].cpu().numpy(), r6["forces"].cpu().numpy(), float(r6["energy"].cpu())))
+        plan_64.close()
         # cold caches: a 512 MiB buffer is rewritten before each timed step
         flush = torch.zeros(128 << 20, dtype=torch.float32, device=dev)
         cold, _, _ = run_loop(torch, plan_ad, pos, q, min(args.steps, 20), args.warmup, "ad", flush=flush)
@@ -629,36 +726,81 @@ def main():
         rb, _, _ = run_loop(torch, plan_ad, pos, q, args.steps, args.warmup, "ad", backward=True)
         out["forward_backward"] = {"ms_per_step": rb["ms_per_step"], "backward_us": rb["backward_us"],
                                    "particles_per_s": n / (rb["ms_per_step"] * 1e-3)}
-        plan_ad.sync()
-        plan_64.sync()
-        out["_gpu_results"] = (f_ad.cpu().numpy().astype(np.float64), float(e_ad.cpu()),
-                               f_64.cpu().numpy(), float(e_64.cpu()), f_ik.cpu().numpy().astype(np.float64))
-        plan_64.close()
+        # energy gradients of the 65,536-charge Gaussian system (64^3, P = 5)
+        # through the autograd form, both precisions
+        w4 = workloads.config(4)
+        for prec, io in (("mixed", torch.float32), ("fp64", torch.float64)):
+            plan4 = pkg.Plan(w4.box_lo, w4.box_len, w4.mesh, w4.order, w4.g_ewald, 1.0, "ad", prec, io,
+                             max_particles=w4.n, device=dev, stream=stream)
+            tp = torch.tensor(w4.pos, dtype=io, device=dev, requires_grad=True)
+            tq = torch.tensor(w4.q, dtype=io, device=dev, requires_grad=True)
+            with torch.cuda.stream(stream):
+                e4 = pkg.pppm_energy(tp, tq, plan4)
+                e4.backward()
+            torch.cuda.synchronize()
+            gpu_res["c4_" + prec] = (tp.grad.cpu().numpy().astype(np.float64), tq.grad.cpu().numpy().astype(np.float64),
+                                     tp.detach().cpu().numpy().astype(np.float64),
+                                     tq.detach().cpu().numpy().astype(np.float64))
+            plan4.close()
+        # the paper's shift-work trade: for each P, the smallest mesh meeting a
+        # force-error target and the step time there
+        out["shift_work"] = shift_work(torch, pkg, workloads, 10, 2, verbose=False)
     plan_ad.close()
 
     if not args.no_cpu_baseline:
-        base, ref = cpu_baseline(w, order, pos_r, q_r)
-        out["cpu_baseline"] = base
-        if "_gpu_results" in out:
-            fa, ea, f64, e64, _ = out["_gpu_results"]
+        from oracle import oracle
 
-            def rms(a, b):
-                return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
-
-            # E = E_mesh + E_self + E_bg nearly cancels for a neutral system;
-            # the mixed form's parity tolerance is taken against the summed
-            # magnitude of the three terms, the scale its FP32 arithmetic
-            # works at
-            terms = abs(ref["e_mesh"]) + abs(ref["e_self"]) + abs(ref["e_bg"])
-            out["error_vs_fp64_oracle"] = {
-                "mixed": {"forces_rms_rel": rms(fa, ref["forces"]),
-                          "energy_rel": abs(ea - ref["energy"]) / abs(ref["energy"]),
-                          "energy_rel_to_terms": abs(ea - ref["energy"]) / terms},
-                "fp64": {"forces_rms_rel": rms(f64, ref["forces"]),
-                         "energy_rel": abs(e64 - ref["energy"]) / abs(ref["energy"])},
-            }
-    out.pop("_gpu_results", None)
+        ref = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ad")
+        out["cpu_baseline"] = cpu_baseline(w, order, pos_r, q_r, ref["phi"])
+        if gpu_res:
+            out["error_vs_fp64_oracle"] = result_errors(oracle, workloads, w, order, pos_r, q_r, ref, gpu_res)
     print(json.dumps(out), flush=True)
+
+
+def kernel_times(torch, plan, forces, reps=30):
+    """Clean per-launch durations of make_rho and fieldforce on a plan whose
+    last call was a full step (see kernel_loop_us); leaves the plan solved."""
+    e = torch.empty((), dtype=torch.float64, device=plan.device)
+    t_ff = kernel_loop_us(torch, plan.stream, lambda: plan.fieldforce(forces), reps)
+    t_rho = kernel_loop_us(torch, plan.stream, lambda: plan.make_rho(None), reps)
+    with torch.cuda.stream(plan.stream):
+        plan.poisson(e)
+    t_poisson = kernel_loop_us(torch, plan.stream, lambda: plan.poisson(e), reps)
+    plan.sync()
+    return {"make_rho": t_rho, "fieldforce": t_ff, "poisson": t_poisson}
+
+
+def result_errors(oracle, workloads, w, order, pos_r, q_r, ref, g):
+    """Each result of the mixed and FP64 forms against the FP64 oracle on the
+    same inputs: mesh charge (max relative), forces (RMS relative and the
+    largest single particle's error over the RMS force), energy (relative),
+    ik forces, and the energy gradients of the 65,536-charge system."""
+
+    def rms(a, b):
+        return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+    def fmax(a, b):
+        return float(np.sqrt(((a - b) ** 2).sum(axis=1)).max() / np.sqrt((b ** 2).sum(axis=1).mean()))
+
+    def rho_rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    res = {}
+    for form in ("mixed", "fp64"):
+        rho, f, e = g[form]
+        res[form] = {"rho_max_rel": rho_rel(rho, ref["rho"]), "forces_rms_rel": rms(f, ref["forces"]),
+                     "forces_max_over_rms": fmax(f, ref["forces"]),
+                     "energy_rel": abs(e - ref["energy"]) / abs(ref["energy"])}
+    ref_ik = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, order, w.g_ewald, 1.0, "ik")
+    res["mixed"]["ik_forces_rms_rel"] = rms(g["ik_forces"], ref_ik["forces"])
+    res["mixed"]["ik_forces_max_over_rms"] = fmax(g["ik_forces"], ref_ik["forces"])
+    w4 = workloads.config(4)
+    for form in ("mixed", "fp64"):
+        gp, gq, p4, q4 = g["c4_" + form]
+        r4 = oracle.energy_gradients(p4, q4, w4.box_lo, w4.box_len, w4.mesh, w4.order, w4.g_ewald, 1.0, "ad")
+        res[form]["c4_grad_pos_rms_rel"] = rms(gp, r4["grad_pos"])
+        res[form]["c4_grad_q_rms_rel"] = rms(gq, r4["grad_q"])
+    return res
 
 
 if __name__ == "__main__":

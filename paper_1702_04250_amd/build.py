@@ -2,8 +2,9 @@
 
     python -m paper_1702_04250_amd.build
 
-compiles every ``csrc/*.hip`` with hipcc into ``paper_1702_04250_amd/lib/``
-(in-tree, so the built library travels with the source tree).
+compiles every ``csrc/*.hip`` with hipcc and every ``csrc/*.cpp`` (host-only
+C++) with g++ into ``paper_1702_04250_amd/lib/`` (in-tree, so the built
+library travels with the source tree).
 """
 from __future__ import annotations
 
@@ -27,6 +28,10 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+
+
+HOST_CXX = "g++"
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 
 def hipcc() -> str:
@@ -54,9 +59,12 @@ def build(verbose: bool = False) -> Path:
     objdir = LIBDIR / "obj"
     objdir.mkdir(exist_ok=True)
     sources = sorted(CSRC.glob("*.hip"))
-    objs = [objdir / (p.stem + ".o") for p in sources]
+    host_sources = sorted(CSRC.glob("*.cpp"))  # plain host C++ (parameter logic)
+    objs = [objdir / (p.stem + ".o") for p in sources + host_sources]
     cmds = [[hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src), "-o", str(obj)]
             for src, obj in zip(sources, objs)]
+    cmds += [[HOST_CXX, *HOST_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src), "-o", str(objdir / (src.stem + ".o"))]
+             for src in host_sources]
     workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "device_common.h"
+#include "params.h"
 #include "pppm_internal.h"
 
 #include <vector>
@@ -44,86 +45,12 @@ pppm_status fail(pppm_plan_s* pl, pppm_status st, const std::string& msg)
             return fail((pl), PPPM_ERR_FFT, std::string(#call) + ": rocfft status " + std::to_string((int)s_)); \
     } while (0)
 
-constexpr int64_t MAX_CELLS = int64_t(1) << 30;
-constexpr int MAX_MESH = 2048;
 constexpr size_t LDS_PREFERRED = 80 * 1024 - 1024;  // keeps two or more workgroups per CU
 constexpr size_t LDS_STATIC = 1024;                 // static LDS of the kernels, rounded up
 
 std::once_flag g_fft_once;
 rocfft_status g_fft_setup = rocfft_status_success;
 
-
-pppm_status validate(const pppm_params* p, std::string& why)
-{
-    if (!p) {
-        why = "params is NULL";
-        return PPPM_ERR_ARG;
-    }
-    if (p->order < 2 || p->order > 7) {
-        why = "order must be in [2, 7], got " + std::to_string(p->order);
-        return PPPM_ERR_ORDER;
-    }
-    int64_t cells = 1;
-    for (int d = 0; d < 3; ++d) {
-        if (!(std::isfinite(p->box_len[d]) && p->box_len[d] > 0.0) || !std::isfinite(p->box_lo[d])) {
-            why = "box_lo must be finite and box_len positive and finite";
-            return PPPM_ERR_ARG;
-        }
-        const int K = p->mesh[d];
-        if (K < 2 || K < p->order || K > MAX_MESH) {
-            why = "mesh[" + std::to_string(d) + "] = " + std::to_string(K) + " must be in [max(2, order), 2048]";
-            return PPPM_ERR_MESH;
-        }
-        cells *= K;
-    }
-    if (cells > MAX_CELLS) {
-        why = "more than 2^30 mesh points";
-        return PPPM_ERR_MESH;
-    }
-    if (!(std::isfinite(p->g_ewald) && p->g_ewald > 0.0)) {
-        why = "g_ewald must be positive and finite";
-        return PPPM_ERR_ARG;
-    }
-    if (!std::isfinite(p->coulomb_c) || p->coulomb_c == 0.0) {
-        why = "coulomb_c must be finite and non-zero";
-        return PPPM_ERR_ARG;
-    }
-    if (p->diff != PPPM_DIFF_IK && p->diff != PPPM_DIFF_AD) {
-        why = "diff must be PPPM_DIFF_IK or PPPM_DIFF_AD";
-        return PPPM_ERR_ARG;
-    }
-    if (p->prec != PPPM_PREC_FP64 && p->prec != PPPM_PREC_MIXED) {
-        why = "prec must be PPPM_PREC_FP64 or PPPM_PREC_MIXED";
-        return PPPM_ERR_DTYPE;
-    }
-    if (p->io_dtype != PPPM_F32 && p->io_dtype != PPPM_F64) {
-        why = "io_dtype must be PPPM_F32 or PPPM_F64";
-        return PPPM_ERR_DTYPE;
-    }
-    if (p->max_particles < 0 || p->max_particles > 2147483647LL) {
-        why = "max_particles must be in [0, 2^31 - 1]";
-        return PPPM_ERR_ARG;
-    }
-    if (p->flags & ~(PPPM_FLAG_CHECK_FINITE | PPPM_FLAG_WEIGHT_TABLE | PPPM_FLAG_AD_SELF_FORCE |
-                     PPPM_WEIGHT_TABLE_SIZE(0xFFFF))) {
-        why = "unknown flag bits";
-        return PPPM_ERR_ARG;
-    }
-    if ((p->flags & PPPM_FLAG_AD_SELF_FORCE) && p->diff != PPPM_DIFF_AD) {
-        why = "PPPM_FLAG_AD_SELF_FORCE needs diff = PPPM_DIFF_AD";
-        return PPPM_ERR_ARG;
-    }
-    const uint32_t tsize = (p->flags >> 8) & 0xFFFFu;
-    if (tsize != 0 && !(p->flags & PPPM_FLAG_WEIGHT_TABLE)) {
-        why = "a weight-table size needs PPPM_FLAG_WEIGHT_TABLE";
-        return PPPM_ERR_ARG;
-    }
-    if (tsize != 0 && tsize < 16) {
-        why = "weight-table size must be at least 16";
-        return PPPM_ERR_ARG;
-    }
-    return PPPM_OK;
-}
 
 // The histogram form of the particle map needs the bins of all tiles in one
 // block's LDS.
@@ -209,17 +136,6 @@ void host_weights(int P, double f, double* w, double* dw)
     }
 }
 
-// A tile edge B along an axis of K points is usable when the axis is a single
-// tile (B >= K), or when every tile, the last (possibly thinner) one
-// included, is at least P - 1 points thick, so that a stencil only ever
-// reaches into the next tile.
-bool edge_ok(int K, int B, int P)
-{
-    if (B >= K) return true;
-    const int rem = K % B;
-    return B >= P - 1 && (rem == 0 || rem >= P - 1);
-}
-
 // Set the plan's tile shape (edges B[3]); returns "" or the reason it is not
 // usable.  Updates the mesh geometry shared by all particle-side kernels.
 std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
@@ -228,7 +144,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     MapGeo g = pl->geo;
     for (int d = 0; d < 3; ++d) {
         if (B[d] < 1 || B[d] > 64) return "tile edges must be in [1, 64]";
-        if (!edge_ok(g.K[d], B[d], P))
+        if (!tile_edge_ok(g.K[d], B[d], P))
             return "tile edge " + std::to_string(B[d]) + " along axis " + std::to_string(d) +
                    " leaves a tile thinner than order - 1 points";
         g.B[d] = B[d] < g.K[d] ? B[d] : g.K[d];
@@ -236,7 +152,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     }
     g.ntiles = g.ntile[0] * g.ntile[1] * g.ntile[2];
     g.bin_stride = use_hist_map(pl, (int64_t)g.ntiles * NCLASS) ? 1 : NSUB;
-    const size_t lds_s = spread_lds_bytes(g, pl->rsize);
+    const size_t lds_s = spread_lds_bytes(g);
     const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize);
     const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize);
     const size_t lim = pl->lds_limit - LDS_STATIC < lds_budget ? pl->lds_limit - LDS_STATIC : lds_budget;
@@ -245,27 +161,18 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
         return "tile needs " + std::to_string(lds_s > lds_g ? lds_s : lds_g) + " bytes of LDS";
     const std::string why = ensure_bin_buffers(pl, (int64_t)g.ntiles * NCLASS, g.bin_stride);
     if (!why.empty()) return why;
+    // The atomic form of the particle map counts into count[] and relies on
+    // it starting at zero (its scan clears it again).  The histogram form
+    // leaves its bin totals there, so a switch from that form clears it.
+    if (g.bin_stride == NSUB &&
+        hipMemsetAsync(pl->count, 0, (size_t)g.ntiles * NCLASS * NSUB * sizeof(int), pl->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return "clearing the bin counters failed";
+    }
     pl->geo = g;
     pl->nbins = (int64_t)g.ntiles * NCLASS;
     pl->stage = Stage::Empty;
     return "";
-}
-
-// Edge for an axis of K points near a preferred edge b: b itself when the
-// last tile keeps at least P - 1 points (edges that are multiples of 4 keep
-// the gather's 16-byte staging loads), else about K / b equal tiles, fewer if
-// the last one would be thinner than P - 1.
-int split_edge(int K, int b, int P)
-{
-    // the preferred edge itself when it fits (a thinner last tile is fine)
-    if (b < K && edge_ok(K, b, P)) return b;
-    int n = (K + b / 2) / b;
-    if (n < 1) n = 1;
-    for (; n > 1; --n) {
-        const int B = (K + n - 1) / n;
-        if (B <= 64 && edge_ok(K, B, P)) return B;
-    }
-    return K;  // a single tile
 }
 
 // Default tile: the first usable shape of a preference list, each axis split
@@ -297,7 +204,7 @@ std::string default_tile(pppm_plan_s* pl)
         for (int k = 0; k < nprefs; ++k) {
             const int* pref = prefs[k];
             int B[3];
-            for (int d = 0; d < 3; ++d) B[d] = split_edge(pl->geo.K[d], pref[d], pl->p.order);
+            for (int d = 0; d < 3; ++d) B[d] = split_tile_edge(pl->geo.K[d], pref[d], pl->p.order);
             if (B[0] > 64 || B[1] > 64 || B[2] > 64) {
                 why = "mesh axis too long for a single tile";
                 continue;
@@ -467,7 +374,7 @@ extern "C" {
 pppm_status pppm_validate(const pppm_params* params)
 {
     std::string why;
-    pppm_status st = validate(params, why);
+    pppm_status st = validate_params(params, why);
     if (st != PPPM_OK) return fail(nullptr, st, why);
     return PPPM_OK;
 }
@@ -477,7 +384,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     if (!out) return fail(nullptr, PPPM_ERR_ARG, "out is NULL");
     *out = nullptr;
     std::string why;
-    pppm_status st = validate(params, why);
+    pppm_status st = validate_params(params, why);
     if (st != PPPM_OK) return fail(nullptr, st, why);
 
     auto* pl = new pppm_plan_s();

@@ -161,7 +161,7 @@ hipError_t launch_own_fft_twiddles(pppm_plan_s* pl);
 hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only, double* energy_out);
 
 // LDS bytes a kernel needs for the plan's tile shape.
-size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes);
+size_t spread_lds_bytes(const MapGeo& g);
 size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 

@@ -19,15 +19,38 @@
 // FP32 contribution q wx wy wz is rounded to an integer multiple of 2^-e and
 // added with ds_add_u32.  Integer addition is associative (modulo 2^32), so
 // the sum is exact and independent of the order of the atomics, and it is
-// correct whenever the final value fits, |rho_m| 2^e < 2^31.  e is chosen per
-// tile from a bound on any of its points: each charge read by the tile adds
-// at most max|q| wmax(P)^3 to a point, with one bit of headroom.  The flush
+// correct whenever the final value fits, |rho_m| 2^e < 2^31 (intermediate
+// sums may wrap).  e is chosen per tile from a bound on any of its points:
+// a charge adds at most max|q| wmax(P)^3 to a point, and only charges whose
+// stencil starts within P - 1 points below it reach it.  A first pass counts
+// the tile's charges per coarse cell of 4^3 stencil starts; the bound of a
+// point is then that count summed over the cells that can hold the starts
+// of its covering stencils, times max|q| wmax^3, with one bit of headroom.
+// At the mean density of the benchmark systems this is about eight times
+// finer than bounding by all the charges the tile reads.  A tile that reads
+// more than WIDE_VISITS charges (a dense cluster) skips the count and sums
+// the same 32-bit rounded contributions in 64 bits (ds_add_u64), with the
+// unit set by the largest single contribution.
+// The rounding is unbiased: each contribution v is rounded to floor(v + d)
+// with a dither d in [0, 1) that is a hash of the charge's record and of the
+// stencil point, so its expectation is v.  Rounding to nearest instead sends
+// every contribution smaller than half a unit to zero; the far corners of
+// the stencils are such contributions for every charge alike, so each
+// charge's mesh cloud loses the same sliver of charge, and the mesh energy,
+// which sums q_i^2 times each cloud's self-interaction, moves coherently
+// over all charges (by 1.2e-5 of E on 524,288 +-1 charges at 128^3, P = 5,
+// where E_mesh and E_self cancel to 1/15).  With the dither the errors are
+// zero-mean and average out over the charges.  The dither depends only on
+// the record's bits (position within the tile and charge), so the sum stays
+// independent of the order of the charges.  The flush
 // converts each exact sum to FP64; that value goes to the caller's FP64 mesh
 // when one is asked for, and, rounded to FP32, to the plan's FFT input (the
 // mixed form transforms in FP32).  The FP64 form does the same in 64-bit
 // fixed point (FP64 products rounded to integers, ds_add_u64, 2^62 bound):
 // faster than ds_add_f64 and, like the mixed form, independent of the order
 // of the atomics; it keeps an FP64 FFT input.
+#include <algorithm>
+
 #include "tiles.h"
 
 namespace pppm {
@@ -44,6 +67,10 @@ struct SpreadArgs {
     int pitch_x;          // LDS row pitch (points): B_x + 2 (P - 1)
     int rows_y;           // LDS rows per plane: B_y, + P - 1 on a single-tile axis
     int planes_z;         // LDS planes: B_z, + P - 1 on a single-tile axis
+    int occ_off;          // byte offset of the occupancy grid in LDS
+    int occ_s[3];         // coarse cell edge per axis (mesh points)
+    int occ_n[3];         // coarse cells per axis
+    int occ_k[3];         // cells below a point's cell that its covering stencils can start in
 };
 
 // Largest value of the order-P B-spline (P = 2..7), rounded up.
@@ -52,77 +79,165 @@ __host__ __device__ constexpr double bspline_max(int P)
     return P == 2 ? 1.0 : P == 3 ? 0.7501 : P == 4 ? 0.6668 : P == 5 ? 0.5991 : P == 6 ? 0.5501 : 0.5111;
 }
 
-// Fixed-point exponent of a tile reading `visits` charges (see above) for a
-// BITS-bit accumulator: the bound times 2^e stays below 2^(BITS - 2), one bit
-// of headroom.
+// Fixed-point exponent for a BITS-bit accumulator when at most `visits`
+// charges reach any point (see above): the bound times 2^e stays below
+// 2^(BITS - 2), one bit of headroom.  The 32-bit form also keeps every single
+// contribution below 2^22 units, so that the FP32 sum v + d of the dithered
+// rounding resolves the dither to at least 2^-2 of a unit (in sparse tiles
+// the bound alone would allow contributions of up to 2^30 units).
 template <int P, int BITS>
 __device__ __forceinline__ int fixed_point_exponent(int visits, double qmax)
 {
     const double wm = bspline_max(P);
-    const double bound = (double)visits * qmax * wm * wm * wm;
-    if (!(bound > 0.0)) return BITS - 2;
+    const double one = qmax * wm * wm * wm;
+    const double bound = (double)visits * one;
+    if (!(bound > 0.0)) return BITS == 32 ? 22 : BITS - 2;
     int e = (int)floor(log2(ldexp(1.0, BITS - 2) / bound));
+    if (BITS == 32) {
+        const int ec = (int)floor(log2(ldexp(1.0, 22) / one));
+        e = e < ec ? e : ec;
+    }
     return e < -60 ? -60 : (e > 120 ? 120 : e);
 }
 
+// Mixed form, dense tiles: above WIDE_VISITS charges the 32-bit bound would
+// round too coarsely (the unit grows with the visits while a point's charge
+// grows about as their square root), so such a tile sums in 64 bits and the
+// exponent only has to keep one contribution below 2^22 units; the sum of at
+// most 2^31 of them stays far inside 2^63.
+constexpr int WIDE_VISITS = 8192;
+template <int P>
+__device__ __forceinline__ int contribution_exponent(double qmax)
+{
+    const double wm = bspline_max(P);
+    const double one = qmax * wm * wm * wm;
+    if (!(one > 0.0)) return 22;
+    const int e = (int)floor(log2(ldexp(1.0, 22) / one));
+    return e < -60 ? -60 : (e > 120 ? 120 : e);
+}
+
+// Dither of the rounding: a 24-bit hash of the record's four words, as a
+// fraction in [0, 1); the rows of the stencil then take the Weyl sequence
+// d + jy a2 + jz a3 (mod 1) with steps of the 2-D R2 low-discrepancy
+// sequence (powers of the inverse of the plastic number, g^3 = g + 1), so
+// every row's dither is uniform on [0, 1).  The points of a row share their
+// row's dither: each contribution is still rounded without bias, and the
+// dither costs one add and one fract per row rather than per point.
+__device__ __forceinline__ float dither_seed(float4 r)
+{
+    unsigned h = __float_as_uint(r.x) * 0x9E3779B1u;
+    h ^= __float_as_uint(r.y) * 0x85EBCA77u;
+    h ^= __float_as_uint(r.z) * 0xC2B2AE3Du;
+    h ^= __float_as_uint(r.w) * 0x27D4EB2Fu;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (float)(h >> 8) * 0x1p-24f;
+}
+__device__ __forceinline__ float dither_seed(double4) { return 0.0f; }
+constexpr float DITHER_Y = 0.7548776662f, DITHER_Z = 0.5698402910f;
+
+// Adds the contribution a * b (already scaled by 2^e) with dither d.
 template <typename A> struct Acc;
 template <> struct Acc<int> {
-    // round half up, floor(v + 1/2), in one instruction (v_cvt_rpi_i32_f32)
-    __device__ static void add(int* p, float v)
+    // floor(a b + d): one fused multiply-add and v_cvt_flr_i32_f32
+    __device__ static void add(int* p, float a, float b, float d)
     {
+        const float v = __builtin_fmaf(a, b, d);
         int r;
-        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
         atomicAdd(p, r);
     }
 };
 template <> struct Acc<long long> {
-    // FP64 form: 64-bit fixed point, the product rounded to nearest
-    __device__ static void add(long long* p, double v)
+    // FP64 form: 64-bit fixed point, the product rounded to nearest (its
+    // unit, 2^-e with e near 53 for the benchmark systems, is far below the
+    // FP64 rounding of the products, so no dither is needed)
+    __device__ static void add(long long* p, double a, double b, float)
     {
-        atomicAdd((unsigned long long*)p, (unsigned long long)__double2ll_rn(v));
+        atomicAdd((unsigned long long*)p, (unsigned long long)__double2ll_rn(a * b));
+    }
+    // mixed form, dense tile: the same 32-bit dithered rounding, summed in
+    // 64 bits
+    __device__ static void add(long long* p, float a, float b, float d)
+    {
+        const float v = __builtin_fmaf(a, b, d);
+        int r;
+        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+        atomicAdd((unsigned long long*)p, (unsigned long long)(long long)r);
     }
 };
+__device__ __forceinline__ float fract1(float x) { return __builtin_amdgcn_fractf(x); }
 
-template <int P, typename R, typename A, bool TAB>
-__global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
+// Most charges whose stencils can reach any one point of the tile: the
+// charges are counted per coarse cell of their stencil start, and a point's
+// count is the sum over the cells from occ_k below its own cell up to it
+// along each axis (a stencil reaching the point starts at most P - 1 points
+// below it).  Ends with the block synchronised.
+template <typename RT>
+__device__ __forceinline__ int tile_reach(const SpreadArgs& a, const RunTable& rt, int* occ, RT cur, int nown,
+                                          const int (&ext)[3])
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ RunTable rt;
+    __shared__ int wmax[32];
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    const int total = rt.pre[NRUNS];
+    const int H = a.g.halo;
+    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+        const int r = find_run(rt, v);
+        if (v >= nown || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
+        const int shp = rt.shift[r], exp_ = rt.ext[r];
+        const decltype(cur.x) tt[3] = {cur.x, cur.y, cur.z};
+        int c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int sl;
+            decltype(cur.x) f;
+            decode_local(tt[d], (exp_ >> (8 * d)) & 255, sl, f);
+            const int dd = sl + ((shp >> (8 * d)) & 255) - 128;  // in [-H, ext)
+            c[d] = min((dd + H) / a.occ_s[d], a.occ_n[d] - 1);
+        }
+        atomicAdd(&occ[(c[2] * a.occ_n[1] + c[1]) * a.occ_n[0] + c[0]], 1);
+    }
+    __syncthreads();
+    // the cells holding the tile's points and, per point cell, its window
+    int c0[3], nc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c0[d] = min(H / a.occ_s[d], a.occ_n[d] - 1);
+        nc[d] = min((ext[d] - 1 + H) / a.occ_s[d], a.occ_n[d] - 1) - c0[d] + 1;
+    }
+    int best = 0;
+    for (int i = threadIdx.x; i < nc[0] * nc[1] * nc[2]; i += blockDim.x) {
+        const int cx = c0[0] + i % nc[0], cy = c0[1] + (i / nc[0]) % nc[1], cz = c0[2] + i / (nc[0] * nc[1]);
+        int sum = 0;
+        for (int z = max(0, cz - a.occ_k[2]); z <= cz; ++z)
+            for (int y = max(0, cy - a.occ_k[1]); y <= cy; ++y)
+                for (int x = max(0, cx - a.occ_k[0]); x <= cx; ++x) sum += occ[(z * a.occ_n[1] + y) * a.occ_n[0] + x];
+        best = max(best, sum);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
+    __syncthreads();
+    int reach = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) reach = max(reach, wmax[w]);
+    return reach;
+}
+
+// The visits of one tile, the periodic folds and the flush, with accumulator
+// type AC (int: 32-bit fixed point; long long: 64-bit) and unit 2^-e.
+template <int P, typename R, typename AC, bool TAB>
+__device__ __forceinline__ void spread_tile(const SpreadArgs& a, const RunTable& rt, AC* acc, int e,
+                                            typename Rec<R>::T cur, int nown, const int (&T0)[3],
+                                            const int (&ext)[3])
+{
     const MapGeo& g = a.g;
-    constexpr int H = P - 1;  // halo / margin width
-
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    int t[3];
-    tile_coords(g, tile, t);
-    const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
-    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
-
-    // The thread's first visit is an own charge whenever the tile has enough
-    // of them; its record is loaded before the accumulator is cleared.
+    constexpr int H = P - 1;
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
-    const int own0 = a.offsets[tile * NCLASS * g.bin_stride], own1 = a.offsets[(tile + 1) * NCLASS * g.bin_stride];
-    RT cur{};
-    if (own0 + (int)threadIdx.x < own1) cur = rec[own0 + threadIdx.x];
-
-    // Accumulator layout: rows of pitch_x points hold x in [-H, B_x + H)
-    // (x index + H); rows_y rows per plane, planes_z planes.  The x margins
-    // take the parts of stencils that fall outside the tile along x, so the
-    // x loop needs no test; along y and z out-of-tile points are skipped.  On
-    // an axis that is a single tile, stencils wrap: the points past K land in
-    // margin rows / planes (y, z) or the right x margin and are folded back
-    // onto the start of the axis before the flush.
-    A* acc = (A*)smem_raw;
     const int pitch = a.pitch_x;
     const int plane = pitch * a.rows_y;
-    const int nacc = plane * a.planes_z;
-    for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc[i] = A(0);
-    build_run_table(g, t, a.offsets, rt);
-    __syncthreads();
     const int total = rt.pre[NRUNS];
-    int e = 0;
-    if (sizeof(A) == 4) e = fixed_point_exponent<P, 32>(total, a.stats[1]);
-    else e = fixed_point_exponent<P, 64>(total, a.stats[1]);
     const R scale = (R)ldexp(1.0, e);
     // valid y rows / z planes: [0, lim)
     const int lim_y = g.ntile[1] == 1 ? g.K[1] + H : ext[1];
@@ -130,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
 
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
         const int r = find_run(rt, v);
-        if (v >= own1 - own0 || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
+        if (v >= nown || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
         const int shp = rt.shift[r], exp_ = rt.ext[r];
         const R tt[3] = {cur.x, cur.y, cur.z};
         int dd[3];
@@ -159,7 +274,9 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
             w[0][j] *= scale;
         }
         // first point of the stencil; only valid rows and planes are touched
-        A* pz = acc + dd[2] * plane + dd[1] * pitch + (dd[0] + H);
+        AC* pz = acc + dd[2] * plane + dd[1] * pitch + (dd[0] + H);
+        // dither of the plane's first point (mixed form; unused in FP64)
+        float dz = dither_seed(cur);
         // z planes in a rolled loop; the plane's z weight is element 0 of
         // the register array, shifted down one per plane
 #pragma unroll 1
@@ -170,14 +287,16 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
                 for (int jy = 0; jy < P; ++jy) {
                     if (vy >> jy & 1u) {
                         const R wzy = wz * w[1][jy];
-                        A* row = pz + jy * pitch;
+                        AC* row = pz + jy * pitch;
+                        const float dy = fract1(dz + (float)jy * DITHER_Y);
 #pragma unroll
-                        for (int jx = 0; jx < P; ++jx) Acc<A>::add(row + jx, wzy * w[0][jx]);
+                        for (int jx = 0; jx < P; ++jx) Acc<AC>::add(row + jx, wzy, w[0][jx], dy);
                     }
                 }
             }
             vz >>= 1;
             pz += plane;
+            dz = fract1(dz + DITHER_Z);
 #pragma unroll
             for (int j = 0; j < P - 1; ++j) w[2][j] = w[2][j + 1];
         }
@@ -188,7 +307,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
     if (g.ntile[0] == 1) {
         const int rows = a.rows_y * a.planes_z;
         for (int i = threadIdx.x; i < rows * H; i += blockDim.x) {
-            A* row = acc + (i / H) * pitch + H;
+            AC* row = acc + (i / H) * pitch + H;
             const int x = i % H;
             row[x] += row[g.K[0] + x];
         }
@@ -198,7 +317,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
         const int n = ext[0] * H * a.planes_z;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const int x = i % ext[0], y = (i / ext[0]) % H, z = i / (ext[0] * H);
-            A* p = acc + z * plane + H + x;
+            AC* p = acc + z * plane + H + x;
             p[y * pitch] += p[(g.K[1] + y) * pitch];
         }
         __syncthreads();
@@ -207,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
         const int n = ext[0] * ext[1] * H;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const int x = i % ext[0], y = (i / ext[0]) % ext[1], z = i / (ext[0] * ext[1]);
-            A* p = acc + y * pitch + H + x;
+            AC* p = acc + y * pitch + H + x;
             p[z * plane] += p[(g.K[2] + z) * plane];
         }
         __syncthreads();
@@ -222,6 +341,57 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
         const size_t gidx = ((size_t)(T0[2] + lz) * g.K[1] + (T0[1] + ly)) * g.K[0] + (T0[0] + lx);
         ((R*)a.rho)[gidx] = (R)v;
         if (a.rho_user) a.rho_user[gidx] = v;
+    }
+}
+
+template <int P, typename R, typename A, bool TAB>
+__global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ RunTable rt;
+    const MapGeo& g = a.g;
+
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int t[3];
+    tile_coords(g, tile, t);
+    const int T0[3] = {t[0] * g.B[0], t[1] * g.B[1], t[2] * g.B[2]};
+    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
+
+    // The thread's first visit is an own charge whenever the tile has enough
+    // of them; its record is loaded before the accumulator is cleared.
+    using RT = typename Rec<R>::T;
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    const int own0 = a.offsets[tile * NCLASS * g.bin_stride], own1 = a.offsets[(tile + 1) * NCLASS * g.bin_stride];
+    RT cur{};
+    if (own0 + (int)threadIdx.x < own1) cur = rec[own0 + threadIdx.x];
+
+    // Accumulator layout: rows of pitch_x points hold x in [-H, B_x + H)
+    // (x index + H); rows_y rows per plane, planes_z planes.  The x margins
+    // take the parts of stencils that fall outside the tile along x, so the
+    // x loop needs no test; along y and z out-of-tile points are skipped.  On
+    // an axis that is a single tile, stencils wrap: the points past K land in
+    // margin rows / planes (y, z) or the right x margin and are folded back
+    // onto the start of the axis before the flush.  The LDS holds 8 bytes per
+    // point, so that a mixed-form tile can take either accumulator width.
+    long long* acc8 = (long long*)smem_raw;
+    int* occ = (int*)(smem_raw + a.occ_off);
+    const int nacc = a.pitch_x * a.rows_y * a.planes_z;
+    const int nocc = a.occ_n[0] * a.occ_n[1] * a.occ_n[2];
+    for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc8[i] = 0;
+    for (int i = threadIdx.x; i < nocc; i += blockDim.x) occ[i] = 0;
+    build_run_table(g, t, a.offsets, rt);
+    __syncthreads();
+    const int total = rt.pre[NRUNS];
+    const double qmax = a.stats[1];
+    if (sizeof(A) == 8) {
+        spread_tile<P, R, long long, TAB>(a, rt, acc8, fixed_point_exponent<P, 64>(total, qmax), cur, own1 - own0,
+                                          T0, ext);
+    } else if (total > WIDE_VISITS) {
+        spread_tile<P, R, long long, TAB>(a, rt, acc8, contribution_exponent<P>(qmax), cur, own1 - own0, T0, ext);
+    } else {
+        const int reach = tile_reach(a, rt, occ, cur, own1 - own0, ext);
+        spread_tile<P, R, int, TAB>(a, rt, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur,
+                                    own1 - own0, T0, ext);
     }
 }
 
@@ -246,9 +416,43 @@ namespace {
 int spread_rows(const MapGeo& g, int d) { return g.B[d] + (g.ntile[d] == 1 ? g.halo : 0); }
 }  // namespace
 
-size_t spread_lds_bytes(const MapGeo& g, size_t acc_bytes)
+// Coarse cells of the occupancy count per axis: starts lie in [-H, B), so
+// B + H of them, in cells of at least 4 points and at most 16 cells; an axis
+// that is a single tile is one cell (its stencils wrap onto the tile).
+struct OccGeo {
+    int s[3], n[3], k[3];
+};
+OccGeo occ_geo(const MapGeo& g)
 {
-    return (size_t)(g.B[0] + 2 * g.halo) * spread_rows(g, 1) * spread_rows(g, 2) * acc_bytes;
+    OccGeo o{};
+    for (int d = 0; d < 3; ++d) {
+        const int span = g.B[d] + g.halo;
+        if (g.ntile[d] == 1) {
+            o.s[d] = span + 1;
+            o.n[d] = 1;
+            o.k[d] = 0;
+        } else {
+            const int sz = std::max(4, (span + 15) / 16);
+            o.s[d] = sz;
+            o.n[d] = (span + sz - 1) / sz;
+            o.k[d] = (g.halo + sz - 1) / sz;
+        }
+    }
+    return o;
+}
+
+size_t spread_acc_bytes(const MapGeo& g)
+{
+    const size_t b = (size_t)(g.B[0] + 2 * g.halo) * spread_rows(g, 1) * spread_rows(g, 2) * sizeof(long long);
+    return (b + 15) & ~(size_t)15;
+}
+
+// 8 bytes per accumulator point in both forms (see k_spread), then the
+// occupancy count.
+size_t spread_lds_bytes(const MapGeo& g)
+{
+    const OccGeo o = occ_geo(g);
+    return spread_acc_bytes(g) + (size_t)o.n[0] * o.n[1] * o.n[2] * sizeof(int);
 }
 
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
@@ -263,7 +467,14 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
     a.rows_y = spread_rows(pl->geo, 1);
     a.planes_z = spread_rows(pl->geo, 2);
     a.stats = pl->eterms + 6;
-    const size_t lds = spread_lds_bytes(pl->geo, pl->rsize);
+    const OccGeo o = occ_geo(pl->geo);
+    a.occ_off = (int)spread_acc_bytes(pl->geo);
+    for (int d = 0; d < 3; ++d) {
+        a.occ_s[d] = o.s[d];
+        a.occ_n[d] = o.n[d];
+        a.occ_k[d] = o.k[d];
+    }
+    const size_t lds = spread_lds_bytes(pl->geo);
     dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
     const bool tab = pl->geo.wtab != nullptr;
     if (pl->mixed)

@@ -169,3 +169,67 @@ def test_ik_backward_on_meshes_of_the_library_transforms(mesh):
     ep, eq = rms_rel(gp, ref["grad_pos"]), rms_rel(gq, ref["grad_q"])
     print(f"  grad_pos {ep:.3e} grad_q {eq:.3e}", flush=True)
     assert ep <= TOL_ORACLE["mixed"] and eq <= TOL_ORACLE["mixed"]
+
+
+@pytest.mark.parametrize("prec,io", [("fp64", torch.float64), ("mixed", torch.float32)])
+def test_ik_backward_on_a_rocfft_mesh(prec, io):
+    # the ik adjoint on a mesh the library's transforms do not take: the
+    # potential comes from the extra G multiply and one rocFFT real inverse
+    mesh = (18, 20, 13)
+    lo = (-1.0, 0.5, 2.0)
+    length = (19.0, 21.0, 14.5)
+    pos, q = W.random_system(800, length, seed=17, box_lo=lo)
+    print(f"case ik backward rocFFT mesh={mesh} {prec}", flush=True)
+    plan = make_plan(pkg, lo, length, mesh, 5, 0.45, 1.0, "ik", prec, io, len(q))
+    pos_r, q_r = io_round(pos, q, io)
+    tp = torch.tensor(pos_r, dtype=io, device=DEV, requires_grad=True)
+    tq = torch.tensor(q_r, dtype=io, device=DEV, requires_grad=True)
+    e = pkg.pppm_energy(tp, tq, plan)
+    e.backward()
+    torch.cuda.synchronize()
+    plan.sync()
+    gp = tp.grad.cpu().numpy().astype(np.float64)
+    gq = tq.grad.cpu().numpy().astype(np.float64)
+    plan.close()
+    ref = oracle.energy_gradients(pos_r, q_r, lo, length, mesh, 5, 0.45, 1.0, "ik")
+    ep, eq = rms_rel(gp, ref["grad_pos"]), rms_rel(gq, ref["grad_q"])
+    print(f"  grad_pos {ep:.3e} grad_q {eq:.3e}", flush=True)
+    assert ep <= TOL_ORACLE[prec] and eq <= TOL_ORACLE[prec]
+
+
+def test_backward_ignores_positions_changed_after_the_forward(c4):
+    # the C ABI backward reads the charges binned by the forward call, not
+    # pos and q again: values written there in place afterwards do not move
+    # the gradient, which stays that of the forward's energy
+    w, _ = c4
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ad", "fp64", torch.float64, w.n)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=DEV)
+    q = torch.tensor(w.q, dtype=torch.float64, device=DEV)
+    ge = torch.ones((), dtype=torch.float64, device=DEV)
+    plan.compute(pos, q, want_forces=False)
+    gp0, gq0 = plan.energy_backward(ge, pos, q)
+    gp0, gq0 = gp0.clone(), gq0.clone()
+    plan.compute(pos, q, want_forces=False)
+    pos.add_(0.37)
+    q.mul_(-2.0)
+    gp1, gq1 = plan.energy_backward(ge, pos, q)
+    plan.sync()
+    assert torch.equal(gp0, gp1) and torch.equal(gq0, gq1)
+    plan.close()
+
+
+def test_autograd_refuses_positions_changed_in_place(c4):
+    # through PPPMEnergy the saved inputs carry torch's version counter: an
+    # in-place change between forward and backward is an error
+    w, _ = c4
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ad", "fp64", torch.float64, w.n)
+    leaf = torch.tensor(w.pos, dtype=torch.float64, device=DEV, requires_grad=True)
+    pos = leaf * 1.0
+    q = torch.tensor(w.q, dtype=torch.float64, device=DEV)
+    e = pkg.pppm_energy(pos, q, plan)
+    with torch.no_grad():
+        pos.add_(0.1)
+    with pytest.raises(RuntimeError):
+        e.backward()
+    plan.sync()
+    plan.close()

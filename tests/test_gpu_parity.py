@@ -102,6 +102,57 @@ def test_ragged_meshes_and_orders(P, mesh, diff):
     run_and_check(pos, q, lo, length, mesh, P, 0.45, 1.7, diff, "fp64", torch.float64, label="ragged")
 
 
+@pytest.mark.parametrize("P", [3, 5, 7])
+@pytest.mark.parametrize("mesh", [(18, 20, 13), (7, 9, 11), (11, 16, 10)])
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_ragged_meshes_mixed(P, mesh, diff):
+    # sizes the library's transforms do not take (an axis under 8, or not of
+    # the form 2^a m with m in {1, 3, 5, 7, 9}) run on rocFFT; in the mixed
+    # form that is an FP32 real transform pair around the FP32 G multiply
+    if min(mesh) < P:
+        pytest.skip("mesh smaller than the order")
+    lo, length = EDGE_BOX
+    pos, q = W.random_system(900, length, seed=P * 31 + mesh[2], box_lo=lo)
+    run_and_check(pos, q, lo, length, mesh, P, 0.45, 1.7, diff, "mixed", torch.float32, label="ragged mixed")
+
+
+@pytest.mark.parametrize("kind", ["pm1", "one_sign"])
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_dense_cluster(kind, diff):
+    # 200,000 charges in a 16-cell cube (about 200 times the mean density)
+    # at P = 7: the tiles over the cluster read tens of thousands of charges,
+    # which the mixed form sums in 64-bit fixed point
+    w = W.clustered(kind)
+    gpu, ref = run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed",
+                             torch.float32, label=w.name)
+    # the mesh charge inside the cluster, where it is largest, point by point
+    kz, ky, kx = ref["rho"].shape
+    sl = (slice(40, 57), slice(40, 57), slice(40, 57))
+    err = np.abs(gpu["rho"][sl] - ref["rho"][sl]).max() / np.abs(ref["rho"][sl]).max()
+    print(f"  cluster mesh charge {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_tile_switches_between_map_forms():
+    # one plan through the device-atomic and the histogram forms of the
+    # particle map and back again: each form must start from counters the
+    # other leaves behind (the histogram form leaves its bin totals)
+    w = W.config(3, order=5)
+    pos_r, q_r = io_round(w.pos, w.q, torch.float32)
+    ref = oracle_run(pos_r, q_r, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad")
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ad", "mixed", torch.float32, w.n)
+    default_tile, default_threads = plan.get_launch(0)
+    for tile, threads in (((4, 4, 4), 256), (default_tile, default_threads), ((8, 4, 4), 256),
+                          (default_tile, default_threads)):
+        plan.set_launch(0, tile, threads)
+        print(f"case tile switch {tile}", flush=True)
+        gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+        errs, bad = compare(gpu, ref, "mixed")
+        print(f"  errors {errs}", flush=True)
+        assert not bad, f"tile {tile}: {bad}"
+    plan.close()
+
+
 @pytest.mark.parametrize("diff", ["ik", "ad"])
 def test_minimum_mesh_equal_to_order(diff):
     lo, length = EDGE_BOX

@@ -117,3 +117,23 @@ def test_influence_function_is_optimal_for_its_mode(c1_ewald, K):
             err[mode, g_of] = _rms_rel(r["forces"], f_k)
     assert err["ik", "ik"] < 0.8 * err["ik", "ad"]
     assert err["ad", "ad"] < err["ad", "ik"]
+
+
+def test_shift_work_reference_setting_is_converged():
+    # The order/mesh trade study (Section 2.3, Section 4) measures the force
+    # error of each (P, K) against the FP64 path at P = 7 on a mesh of
+    # spacing 0.59 A with g = 0.30, Ewald sums over half a million charges
+    # being out of reach.  On a 592-charge system of the same density,
+    # spacing and split, that setting is within 1e-6 of the exact Ewald
+    # reciprocal forces in both differentiation modes (three orders of
+    # magnitude below the study's tightest target), while a coarse setting
+    # of the same system is measurably worse.
+    L, K = 17.7, 30
+    pos, q = random_system(592, (L,) * 3, seed=21, charge="pm1")
+    _, f_ewald = o.ewald_reciprocal(pos, q, (L,) * 3, 0.3)
+    den = (f_ewald ** 2).sum()
+    for diff in ("ad", "ik"):
+        ref = o.pppm(pos, q, (0, 0, 0), (L,) * 3, (K,) * 3, 7, 0.3, 1.0, diff)
+        assert np.sqrt(((ref["forces"] - f_ewald) ** 2).sum() / den) < 1e-6
+    coarse = o.pppm(pos, q, (0, 0, 0), (L,) * 3, (16,) * 3, 5, 0.3, 1.0, "ad")
+    assert np.sqrt(((coarse["forces"] - f_ewald) ** 2).sum() / den) > 1e-5

@@ -209,6 +209,39 @@ def interfacial(order: int = 5) -> Workload:
                     "524,288 +-1 charges in the lower half (z < L/2) of a 170 A cube, vacuum above")
 
 
+def clustered(kind: str = "pm1", order: int = 7) -> Workload:
+    """Dense cluster: 200,000 charges packed into a cube of 16 mesh cells
+    (21.25 A) of the 170 A box (mesh 128^3), its corner off the tile grid at
+    mesh coordinate 40.3, about 200 times the average density, plus charges
+    spread uniformly over the whole box.  kind "pm1": the cluster is +-1
+    (exactly neutral) with 100,000 uniform +-1 charges; "one_sign": the
+    cluster is all +1, neutralised by 200,000 uniform charges of -1."""
+    if kind not in ("pm1", "one_sign"):
+        raise ValueError(kind)
+    rng = np.random.default_rng(7 if kind == "pm1" else 8)
+    length, K = 170.0, 128
+    h = length / K
+    nc = 200000
+    corner = 40.3 * h
+    cl = corner + rng.uniform(0.0, 16 * h, size=(nc, 3))
+    if kind == "pm1":
+        qc = rng.permutation(np.concatenate([np.ones(nc // 2), -np.ones(nc // 2)]))
+        nu = 100000
+        qu = rng.permutation(np.concatenate([np.ones(nu // 2), -np.ones(nu // 2)]))
+    else:
+        qc = np.ones(nc)
+        nu = nc
+        qu = -np.ones(nu)
+    un = rng.uniform(0.0, length, size=(nu, 3))
+    pos = np.concatenate([cl, un])
+    q = np.concatenate([qc, qu])
+    perm = rng.permutation(len(q))
+    return Workload(f"clustered-{kind}-L170-K128", _wrap(pos[perm], length), q[perm], (0.0,) * 3, (length,) * 3,
+                    (K,) * 3, order, 0.30, ("ad", "ik"), 7 if kind == "pm1" else 8,
+                    f"{nc:,} {'+-1' if kind == 'pm1' else '+1'} charges in a 16-cell cube of a 170 A box plus "
+                    f"{nu:,} uniform charges")
+
+
 def random_system(n: int, box_len, seed: int, charge: str = "gaussian", box_lo=(0.0, 0.0, 0.0)):
     """Small general test system: uniform positions in an orthorhombic box."""
     rng = np.random.default_rng(seed)
