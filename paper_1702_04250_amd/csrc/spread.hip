@@ -67,8 +67,8 @@ struct SpreadArgs {
     int pitch_x;          // LDS row pitch (points): B_x + 2 (P - 1)
     int rows_y;           // LDS rows per plane: B_y, + P - 1 on a single-tile axis
     int planes_z;         // LDS planes: B_z, + P - 1 on a single-tile axis
-    int occ_off;          // byte offset of the occupancy grid in LDS
-    int occ_s[3];         // coarse cell edge per axis (mesh points)
+    int occ_off;          // byte offset of the occupancy count in LDS
+    int occ_shift[3];     // log2 of the coarse cell edge per axis (mesh points)
     int occ_n[3];         // coarse cells per axis
     int occ_k[3];         // cells below a point's cell that its covering stencils can start in
 };
@@ -81,38 +81,33 @@ __host__ __device__ constexpr double bspline_max(int P)
 
 // Fixed-point exponent for a BITS-bit accumulator when at most `visits`
 // charges reach any point (see above): the bound times 2^e stays below
-// 2^(BITS - 2), one bit of headroom.  The 32-bit form also keeps every single
-// contribution below 2^22 units, so that the FP32 sum v + d of the dithered
-// rounding resolves the dither to at least 2^-2 of a unit (in sparse tiles
-// the bound alone would allow contributions of up to 2^30 units).
+// 2^(BITS - 2), one bit of headroom.  In a sparse tile single contributions
+// may reach 2^30 units; from 2^24 units on the FP32 value v is an integer
+// and v + d rounds back to v, so such a contribution is added exactly as
+// the FP32 product (no fixed-point rounding at all).
 template <int P, int BITS>
 __device__ __forceinline__ int fixed_point_exponent(int visits, double qmax)
 {
     const double wm = bspline_max(P);
-    const double one = qmax * wm * wm * wm;
-    const double bound = (double)visits * one;
-    if (!(bound > 0.0)) return BITS == 32 ? 22 : BITS - 2;
-    int e = (int)floor(log2(ldexp(1.0, BITS - 2) / bound));
-    if (BITS == 32) {
-        const int ec = (int)floor(log2(ldexp(1.0, 22) / one));
-        e = e < ec ? e : ec;
-    }
+    const double bound = (double)visits * qmax * wm * wm * wm;
+    if (!(bound > 0.0)) return BITS - 2;
+    const int e = (int)floor(log2(ldexp(1.0, BITS - 2) / bound));
     return e < -60 ? -60 : (e > 120 ? 120 : e);
 }
 
 // Mixed form, dense tiles: above WIDE_VISITS charges the 32-bit bound would
 // round too coarsely (the unit grows with the visits while a point's charge
 // grows about as their square root), so such a tile sums in 64 bits and the
-// exponent only has to keep one contribution below 2^22 units; the sum of at
-// most 2^31 of them stays far inside 2^63.
+// exponent only has to keep one contribution (a 32-bit integer) below 2^30
+// units; the sum of at most 2^31 of them stays far inside 2^63.
 constexpr int WIDE_VISITS = 8192;
 template <int P>
 __device__ __forceinline__ int contribution_exponent(double qmax)
 {
     const double wm = bspline_max(P);
     const double one = qmax * wm * wm * wm;
-    if (!(one > 0.0)) return 22;
-    const int e = (int)floor(log2(ldexp(1.0, 22) / one));
+    if (!(one > 0.0)) return 30;
+    const int e = (int)floor(log2(ldexp(1.0, 30) / one));
     return e < -60 ? -60 : (e > 120 ? 120 : e);
 }
 
@@ -169,42 +164,34 @@ template <> struct Acc<long long> {
 };
 __device__ __forceinline__ float fract1(float x) { return __builtin_amdgcn_fractf(x); }
 
-// Most charges whose stencils can reach any one point of the tile: the
-// charges are counted per coarse cell of their stencil start, and a point's
-// count is the sum over the cells from occ_k below its own cell up to it
-// along each axis (a stencil reaching the point starts at most P - 1 points
-// below it).  Ends with the block synchronised.
+// Tile coordinate of the stencil start of a record read through run r.
 template <typename RT>
-__device__ __forceinline__ int tile_reach(const SpreadArgs& a, const RunTable& rt, int* occ, RT cur, int nown,
-                                          const int (&ext)[3])
+__device__ __forceinline__ void stencil_start(const RunTable& rt, int r, const RT& c, int (&dd)[3])
 {
-    __shared__ int wmax[32];
-    const RT* __restrict__ rec = (const RT*)a.rec;
-    const int total = rt.pre[NRUNS];
-    const int H = a.g.halo;
-    for (int v = threadIdx.x; v < total; v += blockDim.x) {
-        const int r = find_run(rt, v);
-        if (v >= nown || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
-        const int shp = rt.shift[r], exp_ = rt.ext[r];
-        const decltype(cur.x) tt[3] = {cur.x, cur.y, cur.z};
-        int c[3];
+    const int shp = rt.shift[r], exp_ = rt.ext[r];
+    const decltype(c.x) tt[3] = {c.x, c.y, c.z};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            int sl;
-            decltype(cur.x) f;
-            decode_local(tt[d], (exp_ >> (8 * d)) & 255, sl, f);
-            const int dd = sl + ((shp >> (8 * d)) & 255) - 128;  // in [-H, ext)
-            c[d] = min((dd + H) / a.occ_s[d], a.occ_n[d] - 1);
-        }
-        atomicAdd(&occ[(c[2] * a.occ_n[1] + c[1]) * a.occ_n[0] + c[0]], 1);
+    for (int d = 0; d < 3; ++d) {
+        int sl;
+        decltype(c.x) f;
+        decode_local(tt[d], (exp_ >> (8 * d)) & 255, sl, f);
+        dd[d] = sl + ((shp >> (8 * d)) & 255) - 128;  // in [-H, ext)
     }
-    __syncthreads();
-    // the cells holding the tile's points and, per point cell, its window
+}
+
+// Most charges whose stencils can reach any one point of the tile, from the
+// count per coarse cell of stencil starts: a point's count is the sum over
+// the cells from occ_k below its own cell up to it along each axis (a
+// stencil reaching the point starts at most P - 1 points below it).  Adds
+// the block's maximum to wmax[wave]; the caller synchronises.
+__device__ __forceinline__ void reach_bound(const SpreadArgs& a, const int* occ, const int (&ext)[3], int* wmax)
+{
+    const int H = a.g.halo;
     int c0[3], nc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        c0[d] = min(H / a.occ_s[d], a.occ_n[d] - 1);
-        nc[d] = min((ext[d] - 1 + H) / a.occ_s[d], a.occ_n[d] - 1) - c0[d] + 1;
+        c0[d] = min(H >> a.occ_shift[d], a.occ_n[d] - 1);
+        nc[d] = min((ext[d] - 1 + H) >> a.occ_shift[d], a.occ_n[d] - 1) - c0[d] + 1;
     }
     int best = 0;
     for (int i = threadIdx.x; i < nc[0] * nc[1] * nc[2]; i += blockDim.x) {
@@ -218,6 +205,34 @@ __device__ __forceinline__ int tile_reach(const SpreadArgs& a, const RunTable& r
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
+}
+
+__device__ __forceinline__ int occ_cell(const SpreadArgs& a, const int (&dd)[3])
+{
+    const int H = a.g.halo;
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = min((dd[d] + H) >> a.occ_shift[d], a.occ_n[d] - 1);
+    return (c[2] * a.occ_n[1] + c[1]) * a.occ_n[0] + c[0];
+}
+
+// First pass of a 32-bit mixed-form tile whose visits are taken in binned
+// order: the occupancy count and the reach bound.  Ends synchronised.
+template <typename RT>
+__device__ __forceinline__ int count_pass(const SpreadArgs& a, const RunTable& rt, int* occ, int* wmax, RT cur,
+                                          int nown, const int (&ext)[3])
+{
+    const RT* __restrict__ rec = (const RT*)a.rec;
+    const int total = rt.pre[NRUNS];
+    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+        const int r = find_run(rt, v);
+        if (v >= nown || v != (int)threadIdx.x) cur = rec[rt.start[r] + (v - rt.pre[r])];
+        int dd[3];
+        stencil_start(rt, r, cur, dd);
+        atomicAdd(&occ[occ_cell(a, dd)], 1);
+    }
+    __syncthreads();
+    reach_bound(a, occ, ext, wmax);
     __syncthreads();
     int reach = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) reach = max(reach, wmax[w]);
@@ -255,7 +270,18 @@ __device__ __forceinline__ void spread_tile(const SpreadArgs& a, const RunTable&
             int s;
             R f;
             decode_local<R>(tt[d], (exp_ >> (8 * d)) & 255, s, f);
-            stencil_weights<P, R, false, TAB>(f, g, w[d], unused);
+            if constexpr (sizeof(R) == 4 && !TAB) {
+                // mixed form: the polynomials in FP64, each weight rounded
+                // once to FP32 (the FP32 evaluation carries a systematic
+                // error of its rounded coefficients into every charge's
+                // mesh cloud alike; FP64 FMAs issue at the FP32 rate here)
+                double wd[P], ud[P];
+                bspline<P, double, false>((double)f, wd, ud);
+#pragma unroll
+                for (int j = 0; j < P; ++j) w[d][j] = (R)wd[j];
+            } else {
+                stencil_weights<P, R, false, TAB>(f, g, w[d], unused);
+            }
             // tile coordinate of the stencil start: negative for a charge of
             // the lower neighbour
             dd[d] = s + ((shp >> (8 * d)) & 255) - 128;
@@ -332,23 +358,37 @@ __device__ __forceinline__ void spread_tile(const SpreadArgs& a, const RunTable&
         __syncthreads();
     }
 
-    // flush: every point of the tile is owned here; coalesced stores
+    // flush: every point of the tile is owned here; coalesced stores.  The
+    // thread's points are i = threadIdx.x + k blockDim.x in x-fastest order;
+    // their coordinates advance by carries instead of a division per point
+    // (integer division by a runtime value is a long instruction sequence).
     const int ex = ext[0], ey = ext[1], ez = ext[2];
-    const int npts = ex * ey * ez;
-    for (int i = threadIdx.x; i < npts; i += blockDim.x) {
-        const int lx = i % ex, ly = (i / ex) % ey, lz = i / (ex * ey);
-        const double v = ldexp((double)acc[lz * plane + ly * pitch + H + lx], -e);
+    const double unit = ldexp(1.0, -e);
+    const int bq = (int)blockDim.x / ex, bx = (int)blockDim.x - bq * ex;  // step in rows and in x
+    const int by = bq % ey, bz = bq / ey;
+    int lx = (int)threadIdx.x % ex, q = (int)threadIdx.x / ex;
+    int ly = q % ey, lz = q / ey;
+    while (lz < ez) {
+        const double v = (double)acc[lz * plane + ly * pitch + H + lx] * unit;
         const size_t gidx = ((size_t)(T0[2] + lz) * g.K[1] + (T0[1] + ly)) * g.K[0] + (T0[0] + lx);
         ((R*)a.rho)[gidx] = (R)v;
         if (a.rho_user) a.rho_user[gidx] = v;
+        lx += bx;
+        const int cx = lx >= ex ? 1 : 0;
+        lx -= cx * ex;
+        ly += by + cx;
+        const int cy = ly >= ey ? 1 : 0;
+        ly -= cy * ey;
+        lz += bz + cy;
     }
 }
 
 template <int P, typename R, typename A, bool TAB>
-__global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
+__device__ __forceinline__ void spread_kernel(const SpreadArgs& a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ RunTable rt;
+    __shared__ int wmax[16];
     const MapGeo& g = a.g;
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -372,7 +412,7 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
     // an axis that is a single tile, stencils wrap: the points past K land in
     // margin rows / planes (y, z) or the right x margin and are folded back
     // onto the start of the axis before the flush.  The LDS holds 8 bytes per
-    // point, so that a mixed-form tile can take either accumulator width.
+    // point (a 32-bit tile uses the first half), then the occupancy count.
     long long* acc8 = (long long*)smem_raw;
     int* occ = (int*)(smem_raw + a.occ_off);
     const int nacc = a.pitch_x * a.rows_y * a.planes_z;
@@ -383,28 +423,51 @@ __global__ __launch_bounds__(1024) void k_spread(SpreadArgs a)
     __syncthreads();
     const int total = rt.pre[NRUNS];
     const double qmax = a.stats[1];
+    const int nown = own1 - own0;
     if (sizeof(A) == 8) {
-        spread_tile<P, R, long long, TAB>(a, rt, acc8, fixed_point_exponent<P, 64>(total, qmax), cur, own1 - own0,
-                                          T0, ext);
+        spread_tile<P, R, long long, TAB>(a, rt, acc8, fixed_point_exponent<P, 64>(total, qmax), cur, nown, T0, ext);
     } else if (total > WIDE_VISITS) {
-        spread_tile<P, R, long long, TAB>(a, rt, acc8, contribution_exponent<P>(qmax), cur, own1 - own0, T0, ext);
+        spread_tile<P, R, long long, TAB>(a, rt, acc8, contribution_exponent<P>(qmax), cur, nown, T0, ext);
     } else {
-        const int reach = tile_reach(a, rt, occ, cur, own1 - own0, ext);
-        spread_tile<P, R, int, TAB>(a, rt, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur,
-                                    own1 - own0, T0, ext);
+        const int reach = count_pass(a, rt, occ, wmax, cur, nown, ext);
+        spread_tile<P, R, int, TAB>(a, rt, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, nown, T0,
+                                    ext);
     }
 }
 
-template <typename R, typename A, bool TAB>
-hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
+// The mixed form asks for eight wavefronts per SIMD (two 1024-thread
+// workgroups per CU), which its register use allows without spilling; the
+// FP64 form needs more registers and runs with fewer.
+template <int P, bool TAB>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_spread(SpreadArgs a)
+{
+    spread_kernel<P, float, int, TAB>(a);
+}
+template <int P, bool TAB>
+__global__ __launch_bounds__(1024) void k_spread64(SpreadArgs a)
+{
+    spread_kernel<P, double, long long, TAB>(a);
+}
+
+template <int P, bool TAB>
+void launch_spread_p(bool mixed, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
+{
+    if (mixed)
+        k_spread<P, TAB><<<grid, block, lds, st>>>(a);
+    else
+        k_spread64<P, TAB><<<grid, block, lds, st>>>(a);
+}
+
+template <bool TAB>
+hipError_t dispatch_spread(bool mixed, int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
 {
     switch (P) {
-    case 2: k_spread<2, R, A, TAB><<<grid, block, lds, st>>>(a); break;
-    case 3: k_spread<3, R, A, TAB><<<grid, block, lds, st>>>(a); break;
-    case 4: k_spread<4, R, A, TAB><<<grid, block, lds, st>>>(a); break;
-    case 5: k_spread<5, R, A, TAB><<<grid, block, lds, st>>>(a); break;
-    case 6: k_spread<6, R, A, TAB><<<grid, block, lds, st>>>(a); break;
-    case 7: k_spread<7, R, A, TAB><<<grid, block, lds, st>>>(a); break;
+    case 2: launch_spread_p<2, TAB>(mixed, grid, block, lds, st, a); break;
+    case 3: launch_spread_p<3, TAB>(mixed, grid, block, lds, st, a); break;
+    case 4: launch_spread_p<4, TAB>(mixed, grid, block, lds, st, a); break;
+    case 5: launch_spread_p<5, TAB>(mixed, grid, block, lds, st, a); break;
+    case 6: launch_spread_p<6, TAB>(mixed, grid, block, lds, st, a); break;
+    case 7: launch_spread_p<7, TAB>(mixed, grid, block, lds, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -413,14 +476,13 @@ hipError_t dispatch_spread(int P, dim3 grid, dim3 block, size_t lds, hipStream_t
 }  // namespace
 
 namespace {
-int spread_rows(const MapGeo& g, int d) { return g.B[d] + (g.ntile[d] == 1 ? g.halo : 0); }
-}  // namespace
 
 // Coarse cells of the occupancy count per axis: starts lie in [-H, B), so
-// B + H of them, in cells of at least 4 points and at most 16 cells; an axis
-// that is a single tile is one cell (its stencils wrap onto the tile).
+// B + H of them, in cells of a power-of-two edge of at least 4 points and at
+// most 16 cells; an axis that is a single tile is one cell (its stencils
+// wrap onto the tile).
 struct OccGeo {
-    int s[3], n[3], k[3];
+    int shift[3], n[3], k[3];
 };
 OccGeo occ_geo(const MapGeo& g)
 {
@@ -428,32 +490,42 @@ OccGeo occ_geo(const MapGeo& g)
     for (int d = 0; d < 3; ++d) {
         const int span = g.B[d] + g.halo;
         if (g.ntile[d] == 1) {
-            o.s[d] = span + 1;
+            o.shift[d] = 30;
             o.n[d] = 1;
             o.k[d] = 0;
         } else {
-            const int sz = std::max(4, (span + 15) / 16);
-            o.s[d] = sz;
-            o.n[d] = (span + sz - 1) / sz;
-            o.k[d] = (g.halo + sz - 1) / sz;
+            int sh = 2;
+            while ((span + (1 << sh) - 1) >> sh > 16) ++sh;
+            o.shift[d] = sh;
+            o.n[d] = (span + (1 << sh) - 1) >> sh;
+            o.k[d] = (g.halo + (1 << sh) - 1) >> sh;
         }
     }
     return o;
 }
 
-size_t spread_acc_bytes(const MapGeo& g)
-{
-    const size_t b = (size_t)(g.B[0] + 2 * g.halo) * spread_rows(g, 1) * spread_rows(g, 2) * sizeof(long long);
-    return (b + 15) & ~(size_t)15;
-}
+int spread_rows(const MapGeo& g, int d) { return g.B[d] + (g.ntile[d] == 1 ? g.halo : 0); }
 
-// 8 bytes per accumulator point in both forms (see k_spread), then the
-// occupancy count.
-size_t spread_lds_bytes(const MapGeo& g)
+size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// LDS of k_spread: the accumulator (8 bytes per point in both forms, see
+// k_spread), then the occupancy count; the count's offset and the total.
+struct SpreadLds {
+    size_t occ_off, total;
+};
+SpreadLds spread_lds_layout(const MapGeo& g)
 {
     const OccGeo o = occ_geo(g);
-    return spread_acc_bytes(g) + (size_t)o.n[0] * o.n[1] * o.n[2] * sizeof(int);
+    const size_t nacc = (size_t)(g.B[0] + 2 * g.halo) * spread_rows(g, 1) * spread_rows(g, 2);
+    SpreadLds l{};
+    l.occ_off = align16(nacc * sizeof(long long));
+    l.total = l.occ_off + align16((size_t)o.n[0] * o.n[1] * o.n[2] * sizeof(int));
+    return l;
 }
+
+}  // namespace
+
+size_t spread_lds_bytes(const MapGeo& g) { return spread_lds_layout(g).total; }
 
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
 {
@@ -468,20 +540,18 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
     a.planes_z = spread_rows(pl->geo, 2);
     a.stats = pl->eterms + 6;
     const OccGeo o = occ_geo(pl->geo);
-    a.occ_off = (int)spread_acc_bytes(pl->geo);
+    const SpreadLds l = spread_lds_layout(pl->geo);
+    a.occ_off = (int)l.occ_off;
     for (int d = 0; d < 3; ++d) {
-        a.occ_s[d] = o.s[d];
+        a.occ_shift[d] = o.shift[d];
         a.occ_n[d] = o.n[d];
         a.occ_k[d] = o.k[d];
     }
-    const size_t lds = spread_lds_bytes(pl->geo);
+    const size_t lds = l.total;
     dim3 grid(pl->geo.ntiles), block(pl->spread_cfg.threads);
     const bool tab = pl->geo.wtab != nullptr;
-    if (pl->mixed)
-        return tab ? dispatch_spread<float, int, true>(pl->p.order, grid, block, lds, pl->stream, a)
-                   : dispatch_spread<float, int, false>(pl->p.order, grid, block, lds, pl->stream, a);
-    return tab ? dispatch_spread<double, long long, true>(pl->p.order, grid, block, lds, pl->stream, a)
-               : dispatch_spread<double, long long, false>(pl->p.order, grid, block, lds, pl->stream, a);
+    return tab ? dispatch_spread<true>(pl->mixed, pl->p.order, grid, block, lds, pl->stream, a)
+               : dispatch_spread<false>(pl->mixed, pl->p.order, grid, block, lds, pl->stream, a);
 }
 
 }  // namespace pppm

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_cases import compare, gpu_run, io_round, make_plan, oracle_run
+from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, strict_energy_err
 
 pytestmark = pytest.mark.gpu
 
@@ -49,5 +49,6 @@ def test_config5_full_size(c5, diff, prec, io):
     errs, bad = compare(gpu, ref, prec)
     print(f"  errors {errs}", flush=True)
     assert not bad, bad
+    assert strict_energy_err(gpu["energy"], ref) <= TOL[prec]["energy"]
     # the zero charge gets exactly zero force
     assert np.all(gpu["forces"][q_r == 0.0] == 0.0)

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, rho_err, rms_rel
+from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, rho_err, rms_rel, strict_energy_err
 from oracle import oracle
 
 pytestmark = pytest.mark.gpu
@@ -20,7 +20,8 @@ import paper_1702_04250_amd as pkg  # noqa: E402
 PRECS = [("fp64", torch.float64), ("mixed", torch.float32), ("mixed", torch.float64), ("fp64", torch.float32)]
 
 
-def run_and_check(pos, q, box_lo, box_len, mesh, P, g, C, diff, prec, io, launch=None, G=None, label=""):
+def run_and_check(pos, q, box_lo, box_len, mesh, P, g, C, diff, prec, io, launch=None, G=None, label="",
+                  strict_energy=False):
     pos_r, q_r = io_round(pos, q, io)
     plan = make_plan(pkg, box_lo, box_len, mesh, P, g, C, diff, prec, io, len(q))
     if launch:
@@ -32,6 +33,10 @@ def run_and_check(pos, q, box_lo, box_len, mesh, P, g, C, diff, prec, io, launch
     errs, bad = compare(gpu, ref, prec)
     print(f"  errors {errs}", flush=True)
     assert not bad, f"{label}: {bad}"
+    if strict_energy:
+        # one of the path's own configurations: |dE| / |E| within the energy
+        # tolerance outright
+        assert strict_energy_err(gpu["energy"], ref) <= TOL[prec]["energy"]
     # energy terms
     terms = gpu["terms"]
     t = TOL[prec]["energy"]
@@ -45,28 +50,28 @@ def run_and_check(pos, q, box_lo, box_len, mesh, P, g, C, diff, prec, io, launch
 @pytest.mark.parametrize("diff", ["ik", "ad"])
 def test_config1(diff, prec, io):
     w = W.config(1)
-    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C1")
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C1", strict_energy=True)
 
 
 @pytest.mark.parametrize("prec,io", [("fp64", torch.float64), ("mixed", torch.float32)])
 @pytest.mark.parametrize("diff", ["ik", "ad"])
 def test_config2_water(diff, prec, io):
     w = W.config(2)
-    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C2")
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, label="C2", strict_energy=True)
 
 
 @pytest.mark.parametrize("P", [3, 4, 5, 6, 7])
 def test_config3_order_sweep_ad_mixed(P):
     w = W.config(3, order=P)
     run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32,
-                  label=f"C3 P={P}")
+                  label=f"C3 P={P}", strict_energy=True)
 
 
 @pytest.mark.parametrize("diff,prec,io", [("ik", "mixed", torch.float32), ("ad", "fp64", torch.float64),
                                           ("ik", "fp64", torch.float64)])
 def test_config3_p5_other_forms(diff, prec, io):
     w = W.config(3)
-    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, diff, prec, io, label="C3 P=5")
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, diff, prec, io, label="C3 P=5", strict_energy=True)
 
 
 # ---- edge cases --------------------------------------------------------------
@@ -124,7 +129,7 @@ def test_dense_cluster(kind, diff):
     # which the mixed form sums in 64-bit fixed point
     w = W.clustered(kind)
     gpu, ref = run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed",
-                             torch.float32, label=w.name)
+                             torch.float32, label=w.name, strict_energy=True)
     # the mesh charge inside the cluster, where it is largest, point by point
     kz, ky, kx = ref["rho"].shape
     sl = (slice(40, 57), slice(40, 57), slice(40, 57))
@@ -359,7 +364,7 @@ def test_interfacial_slab(diff):
     # half the tiles empty, the rest at twice the average load
     w = W.interfacial()
     run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed", torch.float32,
-                  label="interfacial")
+                  label="interfacial", strict_energy=True)
 
 
 @pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
