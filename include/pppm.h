@@ -174,6 +174,31 @@ pppm_status pppm_fieldforce(pppm_plan plan, void *forces);
 pppm_status pppm_compute(pppm_plan plan, int64_t n, const void *pos, const void *q,
                          double *rho, double *energy, void *forces);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): steps 1-4 as
+ * pppm_compute from the parameters alone, with no plan.  Every buffer of the
+ * transient plan (binned charges, meshes, spectra, influence function,
+ * transform tables) is carved from one static device array of
+ * PPPM_NOALLOC_SCRATCH_BYTES per GPU, which the library holds for the life
+ * of the process; the call allocates nothing and launches no memset (what
+ * must start at zero is cleared by a kernel), so it can be captured.
+ * The influence function and transform tables are rebuilt by every call (at
+ * 128^3 they take about 0.1 ms).  Same arguments, layouts and results as
+ * pppm_compute; hip_stream as in pppm_plan_create.
+ * Limits: the mesh must be one the library's own transforms take (see the
+ * Poisson step above; rocFFT plans allocate), and neither
+ * PPPM_FLAG_WEIGHT_TABLE nor PPPM_FLAG_CHECK_FINITE is taken; parameters that
+ * need more scratch than the array holds (about max_particles * 44 bytes plus
+ * 20 to 40 bytes per mesh point) return PPPM_ERR_ARG, others as
+ * pppm_plan_create and pppm_compute.  Errors are reported through
+ * pppm_last_error(NULL).
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads)
+ * race; order them on one stream or synchronise between them. */
+#define PPPM_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+pppm_status pppm_compute_noalloc(const pppm_params *params, void *hip_stream, int64_t n, const void *pos,
+                                 const void *q, double *rho, double *energy, void *forces);
+
 /* Adjoint of the energy.  Given grad_energy (one FP64 on the device, dL/dE),
  * writes grad_pos = dL/dE * dE/dr_i (N x 3) and grad_q = dL/dE * dE/dq_i (N),
  * device, io_dtype, caller order:

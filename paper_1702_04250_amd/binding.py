@@ -82,6 +82,7 @@ def load():
         "pppm_poisson": [vp, vp],
         "pppm_fieldforce": [vp, vp],
         "pppm_compute": [vp, i64, vp, vp, vp, vp, vp],
+        "pppm_compute_noalloc": [P(Params), vp, i64, vp, vp, vp, vp, vp],
         "pppm_energy_backward": [vp, vp, i64, vp, vp, vp, vp],
         "pppm_energy_terms": [vp, vp],
         "pppm_sync": [vp],
@@ -128,6 +129,35 @@ def make_params(box_lo, box_len, mesh, order, g_ewald, coulomb_c=1.0, diff="ad",
 def validate(params: Params) -> int:
     """pppm_validate: pure host check; returns the status code."""
     return load().pppm_validate(ctypes.byref(params))
+
+
+def compute_noalloc(params: Params, pos, q, want_rho=False, want_energy=True, want_forces=True, stream=None,
+                    out=None):
+    """pppm_compute_noalloc: steps 1-4 without a plan, every device buffer in
+    the library's static scratch array (see include/pppm.h).  pos, q and the
+    outputs are caller tensors on the current device; out may hold
+    preallocated outputs (rho, energy, forces), so that the call itself
+    allocates nothing.  Returns dict(rho, energy, forces)."""
+    lib = load()
+    n = pos.shape[0]
+    dev = pos.device
+    kz = int(params.mesh[2]); ky = int(params.mesh[1]); kx = int(params.mesh[0])
+    out = dict(out or {})
+    if want_rho and out.get("rho") is None:
+        out["rho"] = torch.empty((kz, ky, kx), dtype=torch.float64, device=dev)
+    if want_energy and out.get("energy") is None:
+        out["energy"] = torch.empty((), dtype=torch.float64, device=dev)
+    if want_forces and out.get("forces") is None:
+        out["forces"] = torch.empty((n, 3), dtype=pos.dtype, device=dev)
+    rho = out.get("rho") if want_rho else None
+    energy = out.get("energy") if want_energy else None
+    forces = out.get("forces") if want_forces else None
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    status = lib.pppm_compute_noalloc(ctypes.byref(params), ctypes.c_void_p(st.cuda_stream), n, _ptr(pos), _ptr(q),
+                                      _ptr(rho), _ptr(energy), _ptr(forces))
+    if status != PPPM_OK:
+        raise PPPMError(status, last_error(None))
+    return {"rho": rho, "energy": energy, "forces": forces}
 
 
 def last_error(handle=None) -> str:

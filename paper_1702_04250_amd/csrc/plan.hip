@@ -4,6 +4,7 @@
 //   FFT) -> fieldforce,
 // following the three-step PPPM evaluation of the paper (Section 2.1) with
 // the per-atom stencil setup of Section 3.1 as its own step.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -138,7 +139,9 @@ void host_weights(int P, double f, double* w, double* dw)
 
 // Set the plan's tile shape (edges B[3]); returns "" or the reason it is not
 // usable.  Updates the mesh geometry shared by all particle-side kernels.
-std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
+// With alloc false (the allocation-free call) the bin arrays are left to
+// the caller, which sizes them for the chosen geometry afterwards.
+std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget, bool alloc = true)
 {
     const int P = pl->p.order;
     MapGeo g = pl->geo;
@@ -159,15 +162,18 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
     if ((int64_t)g.ntiles * NCLASS > pl->max_bins) return "tile too fine for the plan's bin arrays";
     if (lds_s > lim || lds_g > lim || lds_a > lim)
         return "tile needs " + std::to_string(lds_s > lds_g ? lds_s : lds_g) + " bytes of LDS";
-    const std::string why = ensure_bin_buffers(pl, (int64_t)g.ntiles * NCLASS, g.bin_stride);
-    if (!why.empty()) return why;
-    // The atomic form of the particle map counts into count[] and relies on
-    // it starting at zero (its scan clears it again).  The histogram form
-    // leaves its bin totals there, so a switch from that form clears it.
-    if (g.bin_stride == NSUB &&
-        hipMemsetAsync(pl->count, 0, (size_t)g.ntiles * NCLASS * NSUB * sizeof(int), pl->stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return "clearing the bin counters failed";
+    if (alloc) {
+        const std::string why = ensure_bin_buffers(pl, (int64_t)g.ntiles * NCLASS, g.bin_stride);
+        if (!why.empty()) return why;
+        // The atomic form of the particle map counts into count[] and relies
+        // on it starting at zero (its scan clears it again).  The histogram
+        // form leaves its bin totals there, so a switch from that form
+        // clears it.
+        if (g.bin_stride == NSUB &&
+            hipMemsetAsync(pl->count, 0, (size_t)g.ntiles * NCLASS * NSUB * sizeof(int), pl->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return "clearing the bin counters failed";
+        }
     }
     pl->geo = g;
     pl->nbins = (int64_t)g.ntiles * NCLASS;
@@ -187,7 +193,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget)
 // per tile from the charges it reads, so a larger tile sums more coarsely
 // (32 x 16 x 16 at P = 7 was faster still, but put the 4.2M-charge mesh
 // charge past 1e-4).
-std::string default_tile(pppm_plan_s* pl)
+std::string default_tile(pppm_plan_s* pl, bool alloc = true)
 {
     static const int prefs_ad[][3] = {{32, 16, 8}, {32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};
     static const int prefs_ik[][3] = {{32, 16, 8}, {32, 8, 16}, {32, 8, 8}, {16, 16, 8},
@@ -209,7 +215,7 @@ std::string default_tile(pppm_plan_s* pl)
                 why = "mesh axis too long for a single tile";
                 continue;
             }
-            why = set_tile(pl, B, budget);
+            why = set_tile(pl, B, budget, alloc);
             if (why.empty()) return "";
         }
     }
@@ -303,6 +309,126 @@ pppm_status make_fft_plans(pppm_plan_s* pl)
     return PPPM_OK;
 }
 
+// The part of plan creation that allocates nothing: parameters, device,
+// mesh geometry, transform shapes and default launch sizes.
+pppm_status init_plan_geometry(pppm_plan_s* pl, const pppm_params* params, void* hip_stream)
+{
+    pl->p = *params;
+    pl->stream = (hipStream_t)hip_stream;
+    pl->mixed = params->prec == PPPM_PREC_MIXED;
+    pl->rsize = pl->mixed ? sizeof(float) : sizeof(double);
+    pl->ncomp = params->diff == PPPM_DIFF_IK ? 3 : 1;
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
+    if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
+    pl->lds_limit = (size_t)lds;
+
+    MapGeo& g = pl->geo;
+    for (int d = 0; d < 3; ++d) {
+        g.lo[d] = params->box_lo[d];
+        g.K[d] = params->mesh[d];
+        g.h[d] = params->box_len[d] / (double)params->mesh[d];
+    }
+    g.shift = 1.0 - 0.5 * params->order;
+    g.halo = params->order - 1;
+    g.check_finite = (params->flags & PPPM_FLAG_CHECK_FINITE) ? 1 : 0;
+    pl->ncell = (int64_t)g.K[0] * g.K[1] * g.K[2];
+    pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
+    // finest tiling accepted: as many bins as tiles with edges of 4 points
+    pl->max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
+    // power-of-two meshes whose transform blocks fit in LDS use the library's
+    // own Poisson passes
+    pl->own_fft = own_fft_supported(g.K, pl->mixed);
+    if (pl->own_fft) {
+        own_fft_shapes(pl);
+        if (!own_fft_shapes_ok(pl) || own_fft_lds_max(pl) + LDS_STATIC > pl->lds_limit) pl->own_fft = false;
+    }
+    if (!pl->own_fft) pl->spec_len = pl->nspec;
+    pl->spread_cfg.threads = 1024;
+    pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;
+    return PPPM_OK;
+}
+
+// Bytes of the plan's device buffers (other than the bin arrays, which
+// follow the tiling).
+struct BufferSizes {
+    size_t records, qpart, rho, rho_hat, spec, field, G, epart, sfc, fft_tw;
+};
+BufferSizes buffer_sizes(const pppm_plan_s* pl)
+{
+    const MapGeo& g = pl->geo;
+    const int64_t nmax = pl->p.max_particles;
+    const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
+    BufferSizes z{};
+    z.records = nmax * (pl->mixed ? sizeof(float4) : sizeof(double4));
+    z.qpart = 3 * ((nmax + MAP_THREADS - 1) / MAP_THREADS + 1) * sizeof(double);
+    z.rho = pl->ncell * pl->rsize;
+    z.rho_hat = pl->spec_len * csz;
+    z.spec = (pl->ncomp + 1) * pl->spec_len * csz;
+    z.field = (pl->ncomp + 1) * pl->ncell * pl->rsize;
+    const int64_t g_len =
+        pl->own_fft ? (int64_t)(g.K[0] / 2 + 1) * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1) : pl->nspec;
+    z.G = g_len * sizeof(double);
+    z.epart = ((pl->own_fft && pl->fz_blocks > 2048) ? pl->fz_blocks : 2048) * sizeof(double);
+    z.sfc = (6 + 6 * (size_t)kspace_blocks(pl->nspec)) * sizeof(double);
+    z.fft_tw = (size_t)(g.K[0] + g.K[1] + g.K[2]) * csz;
+    return z;
+}
+
+// ---- scratch of the allocation-free call ---------------------------------
+// One static array per GPU, holding every device buffer of the transient
+// plan of pppm_compute_noalloc.  In host code its name stands for a host
+// symbol: kernels and copies take the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+__device__ __align__(256) unsigned char scratch[PPPM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};
+
+unsigned char* device_scratch(int dev, std::string& why)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        why = "device index " + std::to_string(dev) + " out of range";
+        return nullptr;
+    }
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (unsigned char*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Zero n 32-bit words (a kernel rather than hipMemsetAsync, so that the call
+// can be captured in a HIP graph).
+__global__ void k_zero_words(unsigned* __restrict__ p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Carves 256-byte aligned buffers out of the scratch array; `used` may run
+// past the capacity, which the caller checks before any buffer is touched.
+struct Carver {
+    unsigned char* base;
+    size_t used;
+    template <typename T> void take(T** ptr, size_t bytes)
+    {
+        used = (used + 255) & ~(size_t)255;
+        *ptr = (T*)(base + used);
+        used += bytes > 0 ? bytes : 256;
+    }
+};
+
 pppm_status check_plan(pppm_plan_s* pl)
 {
     if (!pl) return fail(nullptr, PPPM_ERR_ARG, "plan is NULL");
@@ -388,69 +514,26 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     if (st != PPPM_OK) return fail(nullptr, st, why);
 
     auto* pl = new pppm_plan_s();
-    pl->p = *params;
-    pl->stream = (hipStream_t)hip_stream;
-    pl->mixed = params->prec == PPPM_PREC_MIXED;
-    pl->rsize = pl->mixed ? sizeof(float) : sizeof(double);
-    pl->ncomp = params->diff == PPPM_DIFF_IK ? 3 : 1;
-
     auto bail = [&](pppm_status s) {
         g_last_error = pl->last_error;
         release(pl);
         delete pl;
         return s;
     };
-    hipError_t e = hipGetDevice(&pl->device);
-    if (e != hipSuccess) {
-        pl->last_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
-        return bail(PPPM_ERR_HIP);
-    }
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, pl->device);
-    if (e != hipSuccess) {
-        pl->last_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
-        return bail(PPPM_ERR_HIP);
-    }
-    pl->lds_limit = prop.sharedMemPerBlock;
-
-    MapGeo& g = pl->geo;
-    for (int d = 0; d < 3; ++d) {
-        g.lo[d] = params->box_lo[d];
-        g.K[d] = params->mesh[d];
-        g.h[d] = params->box_len[d] / (double)params->mesh[d];
-    }
-    g.shift = 1.0 - 0.5 * params->order;
-    g.halo = params->order - 1;
-    g.check_finite = (params->flags & PPPM_FLAG_CHECK_FINITE) ? 1 : 0;
-    pl->ncell = (int64_t)g.K[0] * g.K[1] * g.K[2];
-    pl->nspec = (int64_t)(g.K[0] / 2 + 1) * g.K[1] * g.K[2];
-    // finest tiling accepted: as many bins as tiles with edges of 4 points
-    pl->max_bins = (int64_t)((g.K[0] + 3) / 4) * ((g.K[1] + 3) / 4) * ((g.K[2] + 3) / 4) * NCLASS;
-
+    if ((st = init_plan_geometry(pl, params, hip_stream)) != PPPM_OK) return bail(st);
     const int64_t nmax = params->max_particles;
-    const size_t recsz = pl->mixed ? sizeof(float4) : sizeof(double4);
-    const size_t csz = pl->mixed ? sizeof(float2) : sizeof(double2);
-    const int64_t map_blocks = (nmax + MAP_THREADS - 1) / MAP_THREADS + 1;
-    // power-of-two meshes whose transform blocks fit in LDS use the library's
-    // own Poisson passes
-    pl->own_fft = own_fft_supported(g.K, pl->mixed);
-    if (pl->own_fft) {
-        own_fft_shapes(pl);
-        if (!own_fft_shapes_ok(pl) || own_fft_lds_max(pl) + LDS_STATIC > pl->lds_limit) pl->own_fft = false;
-    }
-    const int64_t epart_len = (pl->own_fft && pl->fz_blocks > 2048) ? pl->fz_blocks : 2048;
-    if (!pl->own_fft) pl->spec_len = pl->nspec;
-    const int64_t g_len = pl->own_fft ? (int64_t)(g.K[0] / 2 + 1) * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1) : pl->nspec;
+    const BufferSizes z = buffer_sizes(pl);
+    hipError_t e;
     if ((st = dmalloc(pl, &pl->slot, nmax * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->records, nmax * recsz)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->records, z.records)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->perm, nmax * sizeof(int))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->qpart, 3 * map_blocks * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->rho, pl->ncell * pl->rsize)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->rho_hat, pl->spec_len * csz)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->spec, (pl->ncomp + 1) * pl->spec_len * csz)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->field, (pl->ncomp + 1) * pl->ncell * pl->rsize)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->G, g_len * sizeof(double))) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->epart, epart_len * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->qpart, z.qpart)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho, z.rho)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->rho_hat, z.rho_hat)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->spec, z.spec)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->field, z.field)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->G, z.G)) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->epart, z.epart)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
@@ -467,8 +550,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         return bail(PPPM_ERR_HIP);
     }
     if (params->flags & PPPM_FLAG_AD_SELF_FORCE) {
-        if ((st = dmalloc(pl, &pl->sfc, (6 + 6 * (size_t)kspace_blocks(pl->nspec)) * sizeof(double))) != PPPM_OK)
-            return bail(st);
+        if ((st = dmalloc(pl, &pl->sfc, z.sfc)) != PPPM_OK) return bail(st);
         e = launch_self_force_coef(pl);
         if (e != hipSuccess) {
             pl->last_error = std::string("self-force coefficients: ") + hipGetErrorString(e);
@@ -476,7 +558,7 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         }
     }
     if (pl->own_fft) {
-        if ((st = dmalloc(pl, &pl->fft_tw, (size_t)(g.K[0] + g.K[1] + g.K[2]) * csz)) != PPPM_OK) return bail(st);
+        if ((st = dmalloc(pl, &pl->fft_tw, z.fft_tw)) != PPPM_OK) return bail(st);
         e = launch_own_fft_twiddles(pl);
         if (e != hipSuccess) {
             pl->last_error = std::string("twiddle tables: ") + hipGetErrorString(e);
@@ -487,8 +569,6 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
     }
     if ((params->flags & PPPM_FLAG_WEIGHT_TABLE) && (st = build_weight_table(pl)) != PPPM_OK) return bail(st);
 
-    pl->spread_cfg.threads = 1024;
-    pl->gather_cfg.threads = pl->adjoint_cfg.threads = 512;
     {
         std::string bad = default_tile(pl);
         if (!bad.empty()) {
@@ -581,6 +661,82 @@ pppm_status pppm_energy_backward(pppm_plan plan, const double* grad_energy, int6
         pl->phi_valid = true;
     }
     HIP_TRY(pl, launch_gather(pl, GATHER_ADJOINT, grad_pos, grad_q, grad_energy));
+    return PPPM_OK;
+}
+
+pppm_status pppm_compute_noalloc(const pppm_params* params, void* hip_stream, int64_t n, const void* pos,
+                                 const void* q, double* rho, double* energy, void* forces)
+{
+    std::string why;
+    pppm_status st = validate_params(params, why);
+    if (st != PPPM_OK) return fail(nullptr, st, why);
+    if (params->flags & (PPPM_FLAG_WEIGHT_TABLE | PPPM_FLAG_CHECK_FINITE))
+        return fail(nullptr, PPPM_ERR_ARG,
+                    "the allocation-free call takes neither the weight table nor the checked mode (both need a plan)");
+    if (n < 0 || n > params->max_particles)
+        return fail(nullptr, PPPM_ERR_ARG, "n = " + std::to_string(n) + " outside [0, max_particles]");
+    if (n > 0 && (!pos || !q)) return fail(nullptr, PPPM_ERR_ARG, "pos and q must not be NULL");
+
+    // a transient plan on the host; every device buffer it uses lives in the
+    // scratch array
+    pppm_plan_s pl;
+    if ((st = init_plan_geometry(&pl, params, hip_stream)) != PPPM_OK) return fail(nullptr, st, pl.last_error);
+    if (!pl.own_fft)
+        return fail(nullptr, PPPM_ERR_MESH,
+                    "the allocation-free call needs a mesh of the library's own transforms (rocFFT plans allocate)");
+    why = default_tile(&pl, false);
+    if (!why.empty()) return fail(nullptr, PPPM_ERR_MESH, "no usable tile shape: " + why);
+    unsigned char* base = device_scratch(pl.device, why);
+    if (!base) return fail(nullptr, PPPM_ERR_HIP, why);
+
+    const BufferSizes z = buffer_sizes(&pl);
+    const int64_t nmax = params->max_particles;
+    const int64_t nent = pl.nbins * pl.geo.bin_stride;
+    Carver c{base, 0};
+    c.take(&pl.count, nent * sizeof(int));
+    c.take(&pl.offsets, (nent + 1) * sizeof(int));
+    c.take(&pl.scan_part, 2 * ((nent + SCAN_BLOCK - 1) / SCAN_BLOCK) * sizeof(int));
+    if (pl.geo.bin_stride == 1) {
+        pl.hist_bytes = (size_t)HIST_MAX_BLOCKS * pl.nbins * sizeof(int);
+        c.take(&pl.hist, pl.hist_bytes);
+    }
+    c.take(&pl.slot, nmax * sizeof(int));
+    c.take(&pl.records, z.records);
+    c.take(&pl.perm, nmax * sizeof(int));
+    c.take(&pl.qpart, z.qpart);
+    c.take(&pl.rho, z.rho);
+    c.take(&pl.rho_hat, z.rho_hat);
+    c.take(&pl.spec, z.spec);
+    c.take(&pl.field, z.field);
+    c.take(&pl.G, z.G);
+    c.take(&pl.epart, z.epart);
+    c.take(&pl.eterms, 8 * sizeof(double));
+    c.take(&pl.flags, sizeof(int));
+    c.take(&pl.fft_tw, z.fft_tw);
+    if (params->flags & PPPM_FLAG_AD_SELF_FORCE) c.take(&pl.sfc, z.sfc);
+    pl.bin_capacity = nent;
+    if (c.used > PPPM_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, PPPM_ERR_ARG,
+                    "these parameters need " + std::to_string(c.used) + " bytes of device scratch; the allocation-free "
+                    "call holds " + std::to_string((size_t)PPPM_NOALLOC_SCRATCH_BYTES) +
+                    " per GPU (use a plan, or fewer particles or mesh points)");
+
+    // What must start at zero: the energy terms, the sticky flag and (for the
+    // atomic form of the particle map) the bin counters.  The array keeps
+    // the contents of the last call on this GPU.
+    k_zero_words<<<1, 64, 0, pl.stream>>>((unsigned*)pl.eterms, 16);
+    k_zero_words<<<1, 64, 0, pl.stream>>>((unsigned*)pl.flags, 1);
+    if (pl.geo.bin_stride != 1)
+        k_zero_words<<<(unsigned)std::min<int64_t>((nent + 255) / 256, 1024), 256, 0, pl.stream>>>(
+            (unsigned*)pl.count, nent);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_influence(&pl);
+    if (e == hipSuccess && (params->flags & PPPM_FLAG_AD_SELF_FORCE)) e = launch_self_force_coef(&pl);
+    if (e == hipSuccess) e = launch_own_fft_twiddles(&pl);
+    if (e != hipSuccess) return fail(nullptr, PPPM_ERR_HIP, std::string("plan kernels: ") + hipGetErrorString(e));
+    if ((st = do_particle_map(&pl, n, pos, q)) != PPPM_OK || (st = do_make_rho(&pl, rho)) != PPPM_OK ||
+        (st = do_poisson(&pl, energy)) != PPPM_OK || (forces && (st = do_fieldforce(&pl, forces)) != PPPM_OK))
+        return fail(nullptr, st, pl.last_error);
     return PPPM_OK;
 }
 
