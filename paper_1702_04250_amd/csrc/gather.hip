@@ -70,12 +70,16 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     const int nsl = plane * (g.B[2] + P - 1);  // one staged mesh
     const R* __restrict__ fg = (const R*)a.field;
 
-    // The thread's first charge is loaded before the field is staged.
+    // The thread's first charge (record and caller index) is loaded before
+    // the field is staged.
     using RT = typename Rec<R>::T;
     const RT* __restrict__ rec = (const RT*)a.rec;
     RT pr{};
-    int iu = 0;
-    if (first + (int)threadIdx.x < last) pr = rec[first + threadIdx.x];
+    int pm = 0;
+    if (first + (int)threadIdx.x < last) {
+        pr = rec[first + threadIdx.x];
+        if (sizeof(R) == 4) pm = a.perm[first + threadIdx.x];
+    }
 
     // stage tile + upper halo of every field mesh (periodic wrap)
     if (a.vec_stage) {
@@ -86,7 +90,9 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
         const int sx = ext[0] + P - 1, sy = ext[1] + P - 1, sz = ext[2] + P - 1;
         const int nch = (sx + VW - 1) / VW;  // chunks per row
         const int n = nch * sy * sz;
-        constexpr int U = 2;
+        // all of a thread's chunks in flight before the first LDS store (one
+        // round trip for the 1-mesh forms at P <= 7 and 512 threads)
+        constexpr int U = NC == 1 ? 8 : 3;
         for (int i0 = 0; i0 < n; i0 += U * blockDim.x) {
             V v[U][NC];
             int li[U], nv[U];
@@ -165,9 +171,16 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     // the reads are conflict-free.  Each chunk of the tile's charges is
     // counting-sorted by the bank of its stencil start, and sorted position k
     // goes to wavefront k % nw, lane k / nw: each wavefront gets every nw-th
-    // key in sorted order, i.e. starts spread over all banks.
-    int* sidx = (int*)(smem_raw + a.sort_off);  // [blockDim] sorted charge positions
-    int* khist = sidx + blockDim.x;              // [64] bank histogram, then its prefix
+    // key in sorted order, i.e. starts spread over all banks.  In the mixed
+    // form the records and caller indices move through LDS in the sort, and
+    // the next chunk's are loaded while this one is summed; the FP64 form
+    // sorts positions only and reads the records again (its LDS goes to the
+    // staged field).
+    constexpr bool MOVE = sizeof(R) == 4;
+    RT* srec = (RT*)(smem_raw + a.sort_off);  // [blockDim] records in sorted order (mixed)
+    int* sperm = MOVE ? (int*)(srec + blockDim.x) : (int*)(smem_raw + a.sort_off);  // [blockDim] caller
+                                                                                   // indices / positions
+    int* khist = sperm + blockDim.x;           // [64] bank histogram, then its prefix
     constexpr int KEYS = sizeof(R) == 4 ? 64 : 32;  // banks spanned by distinct starts
 
     int l[3] = {0, 0, 0};
@@ -175,7 +188,6 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
     for (int c0 = first; c0 < last; c0 += blockDim.x) {
         const int cnt = min((int)blockDim.x, last - c0);
         const bool have = (int)threadIdx.x < cnt;
-        if (c0 != first && have) pr = rec[c0 + threadIdx.x];
         int key = 0;
         if (have) {
             const R tt[3] = {pr.x, pr.y, pr.z};
@@ -188,7 +200,9 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
             key = (s3[2] * plane + s3[1] * a.pitch_x + s3[0]) & (KEYS - 1);
         }
         if (threadIdx.x < 64) khist[threadIdx.x] = 0;
-        __syncthreads();  // also completes the staging of the first chunk
+        // also completes the staging (first chunk) and the previous chunk's
+        // reads of the sort buffers
+        __syncthreads();
         const int rank = have ? atomicAdd(&khist[key], 1) : 0;
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -196,16 +210,36 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
             khist[threadIdx.x] = wave_inclusive_scan(v) - v;
         }
         __syncthreads();
-        if (have) sidx[khist[key] + rank] = c0 + (int)threadIdx.x;
+        if (have) {
+            const int dst = khist[key] + rank;
+            if constexpr (MOVE) {
+                srec[dst] = pr;
+                sperm[dst] = pm;
+            } else {
+                sperm[dst] = c0 + (int)threadIdx.x;
+            }
+        }
+        const int nx = c0 + (int)blockDim.x + (int)threadIdx.x;
+        if (nx < last) {
+            pr = rec[nx];
+            if constexpr (MOVE) pm = a.perm[nx];
+        }
         __syncthreads();
         const int nw = (cnt + 63) >> 6;
         const int k = (threadIdx.x & 63) * nw + (int)(threadIdx.x >> 6);
         if ((int)(threadIdx.x >> 6) < nw && k < cnt) {
-            const int pc = sidx[k];
-            pr = rec[pc];
-            iu = a.perm[pc];
+            RT r;
+            int iu;
+            if constexpr (MOVE) {
+                r = srec[k];
+                iu = sperm[k];
+            } else {
+                const int pc = sperm[k];
+                r = rec[pc];
+                iu = a.perm[pc];
+            }
             {
-                const R tt[3] = {pr.x, pr.y, pr.z};
+                const R tt[3] = {r.x, r.y, r.z};
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     R f;
@@ -267,7 +301,7 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                 }
             }
             TO* out = (TO*)a.out0;
-            const R qv = pr.w;
+            const R qv = r.w;
             if (MODE == GATHER_IK) {
                 out[3 * (size_t)iu + 0] = (TO)(qv * o0);
                 out[3 * (size_t)iu + 1] = (TO)(qv * o1);
@@ -278,8 +312,7 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                     // self-force q^2 (c1_d sin(2 pi f_d) + c2_d sin(4 pi f_d)) with f_d the
                     // stencil fraction (re-read from the record); c1 carries the sign
                     // that turns sin(2 pi f) into sin(2 pi u) for odd orders
-                    const RT p2 = rec[sidx[k]];
-                    const R tt[3] = {p2.x, p2.y, p2.z};
+                    const R tt[3] = {r.x, r.y, r.z};
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         int sd;
@@ -302,7 +335,6 @@ __global__ __launch_bounds__(512) void k_gather(GatherArgs a)
                     ((TO*)a.out1)[iu] = (TO)(gE * ((double)o3 - a.self_coef * qd - a.bg_coef * Q));
             }
         }
-        __syncthreads();  // the sort buffers are reused by the next chunk
     }
 }
 
@@ -342,18 +374,28 @@ hipError_t dispatch_types(const pppm_plan_s* pl, dim3 grid, dim3 block, size_t l
 
 }  // namespace
 
-// LDS of the staged field meshes (tile + upper halo), rounded up to 16 bytes.
+// LDS of the staged field meshes (tile + upper halo), rounded up to 32 bytes
+// (the alignment of the sorted records that follow).
 size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
 {
     const size_t b = (size_t)ncomp * (g.B[0] + order - 1) * (g.B[1] + order - 1) * (g.B[2] + order - 1) * elem_bytes;
-    return (b + 15) & ~(size_t)15;
+    return (b + 31) & ~(size_t)31;
+}
+
+// LDS of the lane-assignment buffers of a workgroup of `threads`: per thread
+// a record (4 reals, mixed form only) and an index, and the 64-entry bank
+// histogram.
+static size_t gather_sort_lds_bytes(int threads, size_t elem_bytes)
+{
+    const size_t per = (elem_bytes == 4 ? 4 * elem_bytes : 0) + sizeof(int);
+    return (size_t)threads * per + 64 * sizeof(int);
 }
 
 // Total LDS of a gather launch at the largest workgroup (512 threads): the
 // staged meshes plus the lane-assignment buffers.
 size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
 {
-    return gather_field_lds_bytes(g, order, ncomp, elem_bytes) + (512 + 64) * sizeof(int);
+    return gather_field_lds_bytes(g, order, ncomp, elem_bytes) + gather_sort_lds_bytes(512, elem_bytes);
 }
 
 hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy)
@@ -385,7 +427,7 @@ hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, cons
     dim3 grid(pl->geo.ntiles), block(c.threads);
     const int nc = mode == GATHER_IK ? 3 : 1;
     a.sort_off = (int)gather_field_lds_bytes(pl->geo, P, nc, rs);
-    const size_t lds = a.sort_off + (size_t)(c.threads + 64) * sizeof(int);
+    const size_t lds = a.sort_off + gather_sort_lds_bytes(c.threads, rs);
     switch (mode) {
     case GATHER_IK:
         a.field = pl->field;
