@@ -299,8 +299,11 @@ __device__ __forceinline__ void spread_tile(const SpreadArgs& a, const RunTable&
             w[2][j] *= qv;
             w[0][j] *= scale;
         }
-        // first point of the stencil; only valid rows and planes are touched
-        AC* pz = acc + dd[2] * plane + dd[1] * pitch + (dd[0] + H);
+        // first point of the stencil (24-bit products: |dd| < 2^7, plane <
+        // 2^16); only valid rows and planes are touched.  A row's address is
+        // this lane's first point plus a wave-uniform offset (scalar
+        // arithmetic), one vector add per row.
+        AC* const p0 = acc + (__mul24(dd[2], plane) + __mul24(dd[1], pitch) + (dd[0] + H));
         // dither of the plane's first point (mixed form; unused in FP64)
         float dz = dither_seed(cur);
         // z planes in a rolled loop; the plane's z weight is element 0 of
@@ -309,19 +312,20 @@ __device__ __forceinline__ void spread_tile(const SpreadArgs& a, const RunTable&
         for (int jz = 0; jz < P; ++jz) {
             if (vz & 1u) {
                 const R wz = w[2][0];
+                const int zoff = __builtin_amdgcn_readfirstlane(jz * plane);
 #pragma unroll
                 for (int jy = 0; jy < P; ++jy) {
                     if (vy >> jy & 1u) {
                         const R wzy = wz * w[1][jy];
-                        AC* row = pz + jy * pitch;
-                        const float dy = fract1(dz + (float)jy * DITHER_Y);
+                        AC* row = p0 + __builtin_amdgcn_readfirstlane(zoff + jy * pitch);
+                        // dz is in [0, 1) already: the first row takes it as it is
+                        const float dy = jy == 0 ? dz : fract1(dz + (float)jy * DITHER_Y);
 #pragma unroll
                         for (int jx = 0; jx < P; ++jx) Acc<AC>::add(row + jx, wzy, w[0][jx], dy);
                     }
                 }
             }
             vz >>= 1;
-            pz += plane;
             dz = fract1(dz + DITHER_Z);
 #pragma unroll
             for (int j = 0; j < P - 1; ++j) w[2][j] = w[2][j + 1];
