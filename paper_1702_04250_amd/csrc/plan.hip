@@ -189,10 +189,12 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget, bool allo
 // with the full LDS (161 against 167 us at P = 5 on 128^3, 2.03 against
 // 2.29 ms at P = 7 on 256^3, where the tiles that keep the gather's three
 // staged meshes within 79 KiB of LDS were 32 x 8 x 8 and 16 x 8 x 8).
-// Tiles stay at 4,096 points: the mixed form's fixed-point exponent is set
-// per tile from the charges it reads, so a larger tile sums more coarsely
-// (32 x 16 x 16 at P = 7 was faster still, but put the 4.2M-charge mesh
-// charge past 1e-4).
+// Tiles stay at 4,096 points: 8,192-point tiles (32 x 16 x 16, 32 x 32 x 8)
+// halve the bins and the spread's halo pulls but leave the gather one
+// workgroup per CU, so they gain 2 % at P = 5 and 5 % at P = 7 on 128^3 and
+// lose 4 % on the 4.2M-charge 256^3 system (64 x 16 x 8 gains there but
+// doubles the mixed form's error, its coarse occupancy cells being wider
+// along x).
 std::string default_tile(pppm_plan_s* pl, bool alloc = true)
 {
     static const int prefs_ad[][3] = {{32, 16, 8}, {32, 8, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8}, {8, 8, 4}, {4, 4, 4}};

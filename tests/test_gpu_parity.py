@@ -218,21 +218,42 @@ def test_charged_system_background_term():
     assert abs(gpu["terms"][2] - ref["e_bg"]) < 1e-10 * abs(ref["e_bg"])
 
 
-@pytest.mark.parametrize("which,tile,threads", [
+GEOMETRIES = [
     (0, (8, 8, 8), 128), (0, (16, 8, 4), 64), (0, (32, 16, 8), 512), (0, (4, 4, 4), 256), (0, (64, 16, 8), 1024),
     (1, (8, 8, 8), 128), (1, (16, 16, 4), 512), (1, (4, 8, 16), 64), (1, (32, 8, 8), 256),
-])
-@pytest.mark.parametrize("diff", ["ik", "ad"])
-def test_launch_geometries_agree(which, tile, threads, diff):
+]
+# the ik gather stages three field meshes of the shared tile: 64 x 16 x 8 needs
+# more LDS than a workgroup has (test_launch_geometry_beyond_the_lds_is_refused)
+REFUSED = {("ik", 0, (64, 16, 8))}
+
+
+@pytest.mark.parametrize("diff,which,tile,threads",
+                         [(d, *g) for d in ("ik", "ad") for g in GEOMETRIES if (d, g[0], g[1]) not in REFUSED])
+def test_launch_geometries_agree(diff, which, tile, threads):
     w = W.config(2)
-    prec, io = "mixed", torch.float32
-    try:
-        run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io,
-                      launch={which: (tile, threads)}, label=f"launch {which} {tile} {threads}")
-    except pkg.PPPMError as e:
-        # a geometry the device cannot hold is refused on the host, never launched
-        assert e.status == -1
-        pytest.skip(str(e))
+    run_and_check(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, "mixed", torch.float32,
+                  launch={which: (tile, threads)}, label=f"launch {which} {tile} {threads}")
+
+
+def test_launch_geometry_beyond_the_lds_is_refused():
+    # refused on the host (PPPM_ERR_ARG), never launched; the plan keeps its
+    # geometry and still computes to parity
+    w = W.config(2)
+    pos_r, q_r = io_round(w.pos, w.q, torch.float32)
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ik", "mixed", torch.float32, w.n)
+    before = plan.get_launch(0)
+    for diff, which, tile in sorted(REFUSED):
+        with pytest.raises(pkg.PPPMError) as ei:
+            plan.set_launch(which, tile, 1024)
+        assert ei.value.status == -1
+        assert "LDS" in str(ei.value)
+    assert plan.get_launch(0) == before
+    print("case refused geometry, then compute", flush=True)
+    gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+    ref = oracle_run(pos_r, q_r, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, "ik")
+    errs, bad = compare(gpu, ref, "mixed")
+    assert not bad, bad
+    plan.close()
 
 
 def test_nonfinite_input_flag():
