@@ -60,15 +60,21 @@ def parse():
 
 
 def source_hash():
-    """Hash of the HIP sources: counters taken on other sources are stale."""
+    """Hash of the HIP sources' code (comments dropped, whitespace runs
+    collapsed, string literals kept): counters taken on other code are stale."""
     import hashlib
+    import re
 
+    token = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1702_04250_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
+                text = f.read()
+            code = token.sub(lambda m: " " if m.group(0)[0] == "/" else m.group(0), text)
+            code = " ".join(code.split())
+            h.update(name.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
 
 
