@@ -5,6 +5,7 @@
 // following the three-step PPPM evaluation of the paper (Section 2.1) with
 // the per-atom stencil setup of Section 3.1 as its own step.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -137,6 +138,37 @@ void host_weights(int P, double f, double* w, double* dw)
     }
 }
 
+// make_rho's form for tile geometry g, in the mixed form: the push form
+// (k_spread_push + k_fold) at P = 7, where the halo pulls of the
+// owner-computes form double its time (measured on the default tile: 82 vs
+// 88 us on 524,288 charges at 128^3, 692 vs 760 us on 4.2M charges at
+// 256^3; at P = 6 the two are even, at P = 5 the owner-computes form is
+// faster, 37 vs 27 + 16.5 us for the push kernel and its fold).
+// PPPM_SPREAD=push takes the push form at any order, =visit never.  Only
+// when the box fits the LDS; with alloc the box buffer is grown here, and if
+// that fails the plan keeps to the owner-computes form.
+void choose_spread_form(pppm_plan_s* pl, const MapGeo& g, bool alloc)
+{
+    pl->spread_push = false;
+    if (!pl->mixed || pl->spread_mode == 1) return;
+    if (pl->spread_mode == 0 && pl->p.order < 7) return;
+    if (spread_push_lds_bytes(g) > pl->lds_limit - LDS_STATIC) return;
+    if (alloc) {
+        const size_t bytes = (size_t)g.ntiles * spread_box_points(g) * sizeof(float);
+        if (bytes > pl->box_bytes) {
+            float* b = nullptr;
+            if (hipMalloc((void**)&b, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+            if (pl->box) (void)hipFree(pl->box);
+            pl->box = b;
+            pl->box_bytes = bytes;
+        }
+    }
+    pl->spread_push = true;
+}
+
 // Set the plan's tile shape (edges B[3]); returns "" or the reason it is not
 // usable.  Updates the mesh geometry shared by all particle-side kernels.
 // With alloc false (the allocation-free call) the bin arrays are left to
@@ -175,6 +207,7 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget, bool allo
             return "clearing the bin counters failed";
         }
     }
+    choose_spread_form(pl, g, alloc);
     pl->geo = g;
     pl->nbins = (int64_t)g.ntiles * NCLASS;
     pl->stage = Stage::Empty;
@@ -273,7 +306,7 @@ void release(pppm_plan_s* pl)
     if (pl->fft_info) rocfft_execution_info_destroy(pl->fft_info);
     void* bufs[] = {pl->count, pl->offsets, pl->scan_part, pl->slot, pl->records, pl->perm, pl->qpart, pl->hist,
                     pl->rho, pl->rho_hat, pl->spec, pl->field, pl->G, pl->epart, pl->eterms, pl->flags, pl->wtab,
-                    pl->sfc,   pl->fft_tw,  pl->fft_work};
+                    pl->sfc,   pl->fft_tw,  pl->fft_work, pl->box};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -326,6 +359,11 @@ pppm_status init_plan_geometry(pppm_plan_s* pl, const pppm_params* params, void*
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
     if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
     pl->lds_limit = (size_t)lds;
+    // PPPM_SPREAD=visit keeps make_rho to the owner-computes form, =push takes
+    // the push form at every order whenever its box fits the LDS (for
+    // comparisons); otherwise the form follows the order
+    const char* spread_env = std::getenv("PPPM_SPREAD");
+    pl->spread_mode = !spread_env ? 0 : (std::strcmp(spread_env, "visit") == 0 ? 1 : (std::strcmp(spread_env, "push") == 0 ? 2 : 0));
 
     MapGeo& g = pl->geo;
     for (int d = 0; d < 3; ++d) {
@@ -717,6 +755,17 @@ pppm_status pppm_compute_noalloc(const pppm_params* params, void* hip_stream, in
     c.take(&pl.fft_tw, z.fft_tw);
     if (params->flags & PPPM_FLAG_AD_SELF_FORCE) c.take(&pl.sfc, z.sfc);
     pl.bin_capacity = nent;
+    if (pl.spread_push) {
+        // the push form's boxes, when they fit beside the rest; otherwise
+        // make_rho takes the owner-computes form
+        const size_t before = c.used;
+        c.take(&pl.box, (size_t)pl.geo.ntiles * spread_box_points(pl.geo) * sizeof(float));
+        if (c.used > PPPM_NOALLOC_SCRATCH_BYTES) {
+            c.used = before;
+            pl.box = nullptr;
+            pl.spread_push = false;
+        }
+    }
     if (c.used > PPPM_NOALLOC_SCRATCH_BYTES)
         return fail(nullptr, PPPM_ERR_ARG,
                     "these parameters need " + std::to_string(c.used) + " bytes of device scratch; the allocation-free "

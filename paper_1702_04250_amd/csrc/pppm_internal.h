@@ -88,6 +88,10 @@ struct pppm_plan_s {
     int* perm = nullptr;       // [max_particles] binned position -> caller index
     double* qpart = nullptr;   // [3 * map blocks] per block: sum q, sum q^2, max |q|
     void* rho = nullptr;       // [ncell] mesh charge of type R (FP32 in the mixed form), FFT input
+    float* box = nullptr;      // push form of make_rho: [ntiles][box points] FP32 partial sums
+    size_t box_bytes = 0;      // bytes of box
+    bool spread_push = false;  // make_rho in the push form (mixed form, P = 7, box within the LDS)
+    int spread_mode = 0;       // 0: by order, 1: owner-computes form only, 2: push form whenever it fits
     void* rho_hat = nullptr;   // [nspec] complex R
     void* spec = nullptr;      // [(ncomp + 1) * nspec] complex R: field spectra, then phi spectrum
     void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
@@ -162,6 +166,8 @@ hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only, double* energy_out
 
 // LDS bytes a kernel needs for the plan's tile shape.
 size_t spread_lds_bytes(const MapGeo& g);
+size_t spread_push_lds_bytes(const MapGeo& g);
+int64_t spread_box_points(const MapGeo& g);
 size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 

@@ -10,7 +10,9 @@
 // coalesced stores: no global atomics and no zero-fill of the mesh.
 // This is the GPU counterpart of the paper's per-thread private grids
 // ("rethread"): privatise, accumulate, then combine - here the combine is a
-// disjoint ownership of the output.
+// disjoint ownership of the output.  At P = 7 the mixed form takes the push
+// form instead (k_spread_push + k_fold, below): each tile sums only its own
+// charges, whole stencils, and a fold kernel combines the overlapping tiles.
 //
 // Accumulator.  On gfx950 the LDS float atomic add (ds_add_f32) is processed
 // at about one lane every three clocks for any non-uniform address pattern,
@@ -71,6 +73,11 @@ struct SpreadArgs {
     int occ_shift[3];     // log2 of the coarse cell edge per axis (mesh points)
     int occ_n[3];         // coarse cells per axis
     int occ_k[3];         // cells below a point's cell that its covering stencils can start in
+    float* box;           // push form: [ntiles][box_stride] FP32 partial sums of each tile's box
+    int box_stride;       // points of one box: box_pitch * box_rows * box_planes
+    int box_pitch;        // B_x + P - 1
+    int box_rows;         // B_y + P - 1
+    int box_planes;       // B_z + P - 1
 };
 
 // Largest value of the order-P B-spline (P = 2..7), rounded up.
@@ -439,6 +446,211 @@ __device__ __forceinline__ void spread_kernel(const SpreadArgs& a)
     }
 }
 
+// ---- push form (mixed precision) ------------------------------------------
+// Each workgroup sums the whole stencils of its own tile's charges into an
+// LDS box of (B_x + H) x (B_y + H) x (B_z + H) points, H = P - 1: the tile
+// plus the H points past its upper faces that those stencils reach.  No
+// charge is read by another tile and no row is clipped, so every issued LDS
+// atomic lane is live (the owner-computes form above pulls the lower
+// neighbours' charges and clips their stencils to the tile, which leaves
+// about half the atomic lanes idle).  The box is flushed as FP32 partial
+// sums; k_fold then adds, for each mesh point, the boxes of the (up to 8)
+// tiles whose boxes hold it, in a fixed order.  The sums in LDS are the same
+// exact fixed-point sums with the same dithered rounding; the exponent is
+// set from the occupancy count of the tile's own charges.
+
+// Occupancy count of the tile's own charges (stencil starts in [0, ext)),
+// then the reach bound over the box (reach_bound's windows at the occupied
+// cells bound every box point: a point past the tile is reached by a subset
+// of the starts that reach the tile's last points).  Ends synchronised.
+__device__ __forceinline__ int count_pass_own(const SpreadArgs& a, const float4* __restrict__ rec, int own0,
+                                              int nown, int* occ, int* wmax, float4 cur, const int (&ext)[3])
+{
+    for (int v = threadIdx.x; v < nown; v += blockDim.x) {
+        if (v != (int)threadIdx.x) cur = rec[own0 + v];
+        const float tt[3] = {cur.x, cur.y, cur.z};
+        int dd[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float f;
+            decode_local<float>(tt[d], ext[d], dd[d], f);
+        }
+        atomicAdd(&occ[occ_cell(a, dd)], 1);
+    }
+    __syncthreads();
+    reach_bound(a, occ, ext, wmax);
+    __syncthreads();
+    int reach = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) reach = max(reach, wmax[w]);
+    return reach;
+}
+
+template <int P, typename AC, bool TAB>
+__device__ __forceinline__ void push_tile(const SpreadArgs& a, AC* acc, int e, float4 cur, int own0, int nown,
+                                          const int (&ext)[3], float* __restrict__ out)
+{
+    const MapGeo& g = a.g;
+    const float4* __restrict__ rec = (const float4*)a.rec;
+    const int pitch = a.box_pitch;
+    const int plane = pitch * a.box_rows;
+    const float scale = (float)ldexp(1.0, e);
+    for (int v = threadIdx.x; v < nown; v += blockDim.x) {
+        if (v != (int)threadIdx.x) cur = rec[own0 + v];
+        const float tt[3] = {cur.x, cur.y, cur.z};
+        int sl[3];
+        float w[3][P], unused[P];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float f;
+            decode_local<float>(tt[d], ext[d], sl[d], f);
+            if constexpr (!TAB) {
+                // the polynomials in FP64, each weight rounded once to FP32
+                double wd[P], ud[P];
+                bspline<P, double, false>((double)f, wd, ud);
+#pragma unroll
+                for (int j = 0; j < P; ++j) w[d][j] = (float)wd[j];
+            } else {
+                stencil_weights<P, float, false, TAB>(f, g, w[d], unused);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            w[2][j] *= cur.w;
+            w[0][j] *= scale;
+        }
+        // the stencil's first point (box coordinates = tile coordinates);
+        // rows and planes add wave-uniform offsets
+        AC* const p0 = acc + (__mul24(sl[2], plane) + __mul24(sl[1], pitch) + sl[0]);
+        float dz = dither_seed(cur);
+#pragma unroll 1
+        for (int jz = 0; jz < P; ++jz) {
+            const float wz = w[2][0];
+            const int zoff = __builtin_amdgcn_readfirstlane(jz * plane);
+#pragma unroll
+            for (int jy = 0; jy < P; ++jy) {
+                const float wzy = wz * w[1][jy];
+                AC* row = p0 + __builtin_amdgcn_readfirstlane(zoff + jy * pitch);
+                const float dy = jy == 0 ? dz : fract1(dz + (float)jy * DITHER_Y);
+#pragma unroll
+                for (int jx = 0; jx < P; ++jx) Acc<AC>::add(row + jx, wzy, w[0][jx], dy);
+            }
+            dz = fract1(dz + DITHER_Z);
+#pragma unroll
+            for (int j = 0; j < P - 1; ++j) w[2][j] = w[2][j + 1];
+        }
+    }
+    __syncthreads();
+    // flush the whole box (points past a ragged tile's box hold zero)
+    const double unit = ldexp(1.0, -e);
+    const int nbox = plane * a.box_planes;
+    for (int i = threadIdx.x; i < nbox; i += blockDim.x) out[i] = (float)((double)acc[i] * unit);
+}
+
+template <int P, bool TAB>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_spread_push(SpreadArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int wmax[16];
+    const MapGeo& g = a.g;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int t[3];
+    tile_coords(g, tile, t);
+    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
+    const float4* __restrict__ rec = (const float4*)a.rec;
+    const int own0 = a.offsets[tile * NCLASS * g.bin_stride], own1 = a.offsets[(tile + 1) * NCLASS * g.bin_stride];
+    const int nown = own1 - own0;
+    float4 cur{};
+    if ((int)threadIdx.x < nown) cur = rec[own0 + threadIdx.x];
+    // LDS: the box, 8 bytes per point (a 32-bit tile uses the first half),
+    // then the occupancy count
+    long long* acc8 = (long long*)smem_raw;
+    int* occ = (int*)(smem_raw + a.occ_off);
+    const int nocc = a.occ_n[0] * a.occ_n[1] * a.occ_n[2];
+    // a 32-bit tile clears the first half only
+    const int nclear = nown > WIDE_VISITS ? a.box_stride : (a.box_stride + 1) / 2;
+    for (int i = threadIdx.x; i < nclear; i += blockDim.x) acc8[i] = 0;
+    for (int i = threadIdx.x; i < nocc; i += blockDim.x) occ[i] = 0;
+    __syncthreads();
+    float* out = a.box + (size_t)tile * a.box_stride;
+    const double qmax = a.stats[1];
+    if (nown > WIDE_VISITS) {
+        push_tile<P, long long, TAB>(a, acc8, contribution_exponent<P>(qmax), cur, own0, nown, ext, out);
+    } else {
+        const int reach = count_pass_own(a, rec, own0, nown, occ, wmax, cur, ext);
+        push_tile<P, int, TAB>(a, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, own0, nown, ext,
+                               out);
+    }
+}
+
+// Fold of the push form: point (lx, ly, lz) of a tile sums its own box
+// value and, for each set of axes d along which l_d < H, the box value of
+// the lower neighbour across those axes (periodic) at l_d + that
+// neighbour's extent; the up-to-8 terms are added
+// in FP64 in a fixed order (own tile first, then the neighbours by mask).
+// Workgroups take 256 consecutive points of one tile (x fastest), so the
+// own values and the written rows of the mesh are coalesced.
+struct FoldArgs {
+    const float* box;
+    float* rho;          // plan mesh (FFT input), FP32
+    double* rho_user;    // caller's FP64 mesh or null
+    MapGeo g;
+    int pitch, rows, stride;
+};
+
+constexpr int FOLD_THREADS = 256;
+
+__global__ __launch_bounds__(FOLD_THREADS) void k_fold(FoldArgs f)
+{
+    const MapGeo& g = f.g;
+    const int H = g.halo;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int t[3];
+    tile_coords(g, tile, t);
+    const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
+    // one point of the tile per thread: many loads in flight
+    const int i = (int)blockIdx.y * FOLD_THREADS + (int)threadIdx.x;
+    if (i >= ext[0] * ext[1] * ext[2]) return;
+    const int lx = i % ext[0], r = i / ext[0];
+    const int ly = r % ext[1], lz = r / ext[1];
+    const int mask = (lx < H ? 1 : 0) | (ly < H ? 2 : 0) | (lz < H ? 4 : 0);
+    double sum = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if ((m & mask) != m) continue;
+        // the lower neighbour (periodic) across the axes of m, and the point
+        // in its box: l_d + its extent along those axes
+        int c[3] = {lx, ly, lz}, s3[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s3[d] = t[d];
+            if ((m >> d) & 1) {
+                s3[d] = t[d] == 0 ? g.ntile[d] - 1 : t[d] - 1;
+                c[d] += tile_extent(g, d, s3[d]);
+            }
+        }
+        const size_t nb = ((size_t)s3[2] * g.ntile[1] + s3[1]) * g.ntile[0] + s3[0];
+        sum += (double)f.box[nb * f.stride + (c[2] * f.rows + c[1]) * f.pitch + c[0]];
+    }
+    const size_t gi = ((size_t)(t[2] * g.B[2] + lz) * g.K[1] + (t[1] * g.B[1] + ly)) * g.K[0] + (t[0] * g.B[0] + lx);
+    f.rho[gi] = (float)sum;
+    if (f.rho_user) f.rho_user[gi] = sum;
+}
+
+template <bool TAB>
+hipError_t dispatch_push(int P, dim3 grid, dim3 block, size_t lds, hipStream_t st, const SpreadArgs& a)
+{
+    switch (P) {
+    case 2: k_spread_push<2, TAB><<<grid, block, lds, st>>>(a); break;
+    case 3: k_spread_push<3, TAB><<<grid, block, lds, st>>>(a); break;
+    case 4: k_spread_push<4, TAB><<<grid, block, lds, st>>>(a); break;
+    case 5: k_spread_push<5, TAB><<<grid, block, lds, st>>>(a); break;
+    case 6: k_spread_push<6, TAB><<<grid, block, lds, st>>>(a); break;
+    case 7: k_spread_push<7, TAB><<<grid, block, lds, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // The mixed form asks for eight wavefronts per SIMD (two 1024-thread
 // workgroups per CU), which its register use allows without spilling; the
 // FP64 form needs more registers and runs with fewer.
@@ -531,8 +743,62 @@ SpreadLds spread_lds_layout(const MapGeo& g)
 
 size_t spread_lds_bytes(const MapGeo& g) { return spread_lds_layout(g).total; }
 
+// Points of one tile's box in the push form: (B_x + H)(B_y + H)(B_z + H).
+int64_t spread_box_points(const MapGeo& g)
+{
+    return (int64_t)(g.B[0] + g.halo) * (g.B[1] + g.halo) * (g.B[2] + g.halo);
+}
+
+// LDS of k_spread_push: the box at 8 bytes per point, then the occupancy
+// count.
+SpreadLds push_lds_layout(const MapGeo& g)
+{
+    const OccGeo o = occ_geo(g);
+    SpreadLds l{};
+    l.occ_off = align16((size_t)spread_box_points(g) * sizeof(long long));
+    l.total = l.occ_off + align16((size_t)o.n[0] * o.n[1] * o.n[2] * sizeof(int));
+    return l;
+}
+size_t spread_push_lds_bytes(const MapGeo& g) { return push_lds_layout(g).total; }
+
 hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
 {
+    if (pl->spread_push) {
+        const MapGeo& g = pl->geo;
+        SpreadArgs a{};
+        a.g = g;
+        a.offsets = pl->offsets;
+        a.rec = pl->records;
+        a.stats = pl->eterms + 6;
+        a.box = pl->box;
+        a.box_pitch = g.B[0] + g.halo;
+        a.box_rows = g.B[1] + g.halo;
+        a.box_planes = g.B[2] + g.halo;
+        a.box_stride = (int)spread_box_points(g);
+        const OccGeo o = occ_geo(g);
+        const SpreadLds l = push_lds_layout(g);
+        a.occ_off = (int)l.occ_off;
+        for (int d = 0; d < 3; ++d) {
+            a.occ_shift[d] = o.shift[d];
+            a.occ_n[d] = o.n[d];
+            a.occ_k[d] = o.k[d];
+        }
+        dim3 grid(g.ntiles), block(pl->spread_cfg.threads);
+        const hipError_t e = g.wtab ? dispatch_push<true>(pl->p.order, grid, block, l.total, pl->stream, a)
+                                    : dispatch_push<false>(pl->p.order, grid, block, l.total, pl->stream, a);
+        if (e != hipSuccess) return e;
+        FoldArgs f{};
+        f.box = pl->box;
+        f.rho = (float*)pl->rho;
+        f.rho_user = rho_user;
+        f.g = g;
+        f.pitch = a.box_pitch;
+        f.rows = a.box_rows;
+        f.stride = a.box_stride;
+        const int chunks = (g.B[0] * g.B[1] * g.B[2] + FOLD_THREADS - 1) / FOLD_THREADS;
+        k_fold<<<dim3(g.ntiles, chunks), FOLD_THREADS, 0, pl->stream>>>(f);
+        return hipGetLastError();
+    }
     SpreadArgs a{};
     a.g = pl->geo;
     a.offsets = pl->offsets;

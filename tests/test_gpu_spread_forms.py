@@ -1,0 +1,113 @@
+"""make_rho's two forms in the mixed precision, each against the oracle on the
+same inputs: the owner-computes form (each tile pulls the charges whose
+stencils reach it) and the push form (each tile sums its own charges' whole
+stencils into a box extended by P - 1, then a fold adds the overlapping
+boxes).  The plan takes the push form at P = 7 by itself; PPPM_SPREAD forces
+either form at plan creation.  Cases: the benchmark system at P = 5 and 7,
+ragged meshes with axes of one tile (the boxes wrap onto the start of the
+axis), a dense cluster at P = 7 (64-bit box sums), and the mesh charge of
+the FP64 output (the fold also writes the caller's FP64 mesh)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_cases import TOL, compare, gpu_run, io_round, make_plan, oracle_run, strict_energy_err
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1702_04250_amd as pkg  # noqa: E402
+
+
+def plan_in_form(form, box_lo, box_len, mesh, P, g, diff, nmax, launch=None):
+    old = os.environ.get("PPPM_SPREAD")
+    os.environ["PPPM_SPREAD"] = form
+    try:
+        plan = make_plan(pkg, box_lo, box_len, mesh, P, g, 1.0, diff, "mixed", torch.float32, nmax)
+    finally:
+        if old is None:
+            del os.environ["PPPM_SPREAD"]
+        else:
+            os.environ["PPPM_SPREAD"] = old
+    if launch:
+        plan.set_launch(0, *launch)
+    return plan
+
+
+def both_forms(pos, q, box_lo, box_len, mesh, P, g, diff, label, launch=None, strict_energy=False):
+    pos_r, q_r = io_round(pos, q, torch.float32)
+    ref = oracle_run(pos_r, q_r, box_lo, box_len, mesh, P, g, 1.0, diff)
+    out = {}
+    for form in ("visit", "push"):
+        plan = plan_in_form(form, box_lo, box_len, mesh, P, g, diff, len(q), launch)
+        print(f"case {label} {form} n={len(q)} mesh={mesh} P={P} {diff}", flush=True)
+        gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+        plan.close()
+        errs, bad = compare(gpu, ref, "mixed")
+        print(f"  errors {errs}", flush=True)
+        assert not bad, f"{label} {form}: {bad}"
+        if strict_energy:
+            assert strict_energy_err(gpu["energy"], ref) <= TOL["mixed"]["energy"]
+        out[form] = gpu
+    # the two forms round the same contributions with different units: they
+    # agree to about the fixed-point resolution
+    d = np.abs(out["push"]["rho"] - out["visit"]["rho"]).max() / np.abs(ref["rho"]).max()
+    print(f"  push vs owner-computes mesh charge {d:.2e}", flush=True)
+    assert d <= 2 * TOL["mixed"]["rho"]
+    return out, ref
+
+
+@pytest.mark.parametrize("P", [5, 7])
+def test_benchmark_system_in_both_forms(P):
+    w = W.config(3, order=P)
+    both_forms(w.pos, w.q, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", f"uniform 524k P={P}",
+               strict_energy=True)
+
+
+@pytest.mark.parametrize("mesh,P,tile", [
+    ((18, 20, 13), 5, None),        # rocFFT mesh, default tiles
+    ((7, 9, 11), 7, None),          # every axis a single tile: boxes wrap
+    ((40, 24, 30), 4, (16, 8, 12)),  # ragged last tiles (40 = 16+16+8, 30 = 12+12+6)
+    ((32, 16, 20), 3, (32, 4, 8)),   # x a single tile, y thin tiles, z ragged
+    ((16, 16, 16), 2, (8, 8, 8)),
+])
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_ragged_and_single_tile_meshes(mesh, P, tile, diff):
+    lo, length = (-2.0, 1.0, 0.5), (13.0, 15.5, 11.0)
+    pos, q = W.random_system(3000, length, seed=sum(mesh) + P, box_lo=lo)
+    launch = (tile, 512) if tile else None
+    both_forms(pos, q, lo, length, mesh, P, 0.5, diff, f"mesh {mesh} tile {tile}", launch=launch)
+
+
+def test_dense_cluster_in_both_forms():
+    # about 200 times the mean density: the cluster's tiles sum in 64 bits
+    w = W.clustered("one_sign")
+    out, ref = both_forms(w.pos, w.q, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, "ad", w.name,
+                          strict_energy=True)
+    sl = (slice(40, 57), slice(40, 57), slice(40, 57))
+    for form, gpu in out.items():
+        err = np.abs(gpu["rho"][sl] - ref["rho"][sl]).max() / np.abs(ref["rho"][sl]).max()
+        print(f"  {form}: cluster mesh charge {err:.2e}", flush=True)
+        assert err <= 1e-4
+
+
+def test_push_form_is_the_default_at_order_7():
+    # no variable set: P = 7 takes the push form, P = 5 the owner-computes
+    # form; each matches the plan forced to that form bit for bit
+    w = W.config(1)
+    pos_r, q_r = io_round(w.pos, w.q, torch.float32)
+    assert "PPPM_SPREAD" not in os.environ
+    for P, form in ((7, "push"), (5, "visit")):
+        default = make_plan(pkg, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32, w.n)
+        forced = plan_in_form(form, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", w.n)
+        print(f"case default form at P={P}", flush=True)
+        a = gpu_run(default, pos_r, q_r, torch.float32)
+        b = gpu_run(forced, pos_r, q_r, torch.float32)
+        default.close()
+        forced.close()
+        assert np.array_equal(a["rho"], b["rho"]) and a["energy"] == b["energy"]
