@@ -587,8 +587,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 // the lower neighbour across those axes (periodic) at l_d + that
 // neighbour's extent; the up-to-8 terms are added
 // in FP64 in a fixed order (own tile first, then the neighbours by mask).
-// Workgroups take 256 consecutive points of one tile (x fastest), so the
-// own values and the written rows of the mesh are coalesced.
+// The own values and the written rows of the mesh are coalesced.
 struct FoldArgs {
     const float* box;
     float* rho;          // plan mesh (FFT input), FP32
@@ -599,6 +598,9 @@ struct FoldArgs {
 
 constexpr int FOLD_THREADS = 256;
 
+// Workgroup (bx, FOLD_THREADS / bx): x of the tile along threadIdx.x (bx =
+// B_x rounded up to 32, at most 64), rows (y, z) of the tile along
+// threadIdx.y and blockIdx.y; the tile's geometry is uniform per workgroup.
 __global__ __launch_bounds__(FOLD_THREADS) void k_fold(FoldArgs f)
 {
     const MapGeo& g = f.g;
@@ -607,29 +609,26 @@ __global__ __launch_bounds__(FOLD_THREADS) void k_fold(FoldArgs f)
     int t[3];
     tile_coords(g, tile, t);
     const int ext[3] = {tile_extent(g, 0, t[0]), tile_extent(g, 1, t[1]), tile_extent(g, 2, t[2])};
-    // one point of the tile per thread: many loads in flight
-    const int i = (int)blockIdx.y * FOLD_THREADS + (int)threadIdx.x;
-    if (i >= ext[0] * ext[1] * ext[2]) return;
-    const int lx = i % ext[0], r = i / ext[0];
-    const int ly = r % ext[1], lz = r / ext[1];
+    const int lx = threadIdx.x;
+    const int r = (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (lx >= ext[0] || r >= ext[1] * ext[2]) return;
+    const int lz = r / ext[1], ly = r - lz * ext[1];
+    // lower neighbours (periodic) and their extents
+    int tl[3], el[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        tl[d] = t[d] == 0 ? g.ntile[d] - 1 : t[d] - 1;
+        el[d] = tile_extent(g, d, tl[d]);
+    }
     const int mask = (lx < H ? 1 : 0) | (ly < H ? 2 : 0) | (lz < H ? 4 : 0);
     double sum = 0.0;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         if ((m & mask) != m) continue;
-        // the lower neighbour (periodic) across the axes of m, and the point
-        // in its box: l_d + its extent along those axes
-        int c[3] = {lx, ly, lz}, s3[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            s3[d] = t[d];
-            if ((m >> d) & 1) {
-                s3[d] = t[d] == 0 ? g.ntile[d] - 1 : t[d] - 1;
-                c[d] += tile_extent(g, d, s3[d]);
-            }
-        }
-        const size_t nb = ((size_t)s3[2] * g.ntile[1] + s3[1]) * g.ntile[0] + s3[0];
-        sum += (double)f.box[nb * f.stride + (c[2] * f.rows + c[1]) * f.pitch + c[0]];
+        const int sx = (m & 1) ? tl[0] : t[0], sy = (m & 2) ? tl[1] : t[1], sz = (m & 4) ? tl[2] : t[2];
+        const int cx = lx + ((m & 1) ? el[0] : 0), cy = ly + ((m & 2) ? el[1] : 0), cz = lz + ((m & 4) ? el[2] : 0);
+        const float* nb = f.box + (size_t)((sz * g.ntile[1] + sy) * g.ntile[0] + sx) * f.stride;
+        sum += (double)nb[(cz * f.rows + cy) * f.pitch + cx];
     }
     const size_t gi = ((size_t)(t[2] * g.B[2] + lz) * g.K[1] + (t[1] * g.B[1] + ly)) * g.K[0] + (t[0] * g.B[0] + lx);
     f.rho[gi] = (float)sum;
@@ -795,8 +794,10 @@ hipError_t launch_spread(pppm_plan_s* pl, double* rho_user)
         f.pitch = a.box_pitch;
         f.rows = a.box_rows;
         f.stride = a.box_stride;
-        const int chunks = (g.B[0] * g.B[1] * g.B[2] + FOLD_THREADS - 1) / FOLD_THREADS;
-        k_fold<<<dim3(g.ntiles, chunks), FOLD_THREADS, 0, pl->stream>>>(f);
+        const int bx = g.B[0] <= 32 ? 32 : 64;
+        const int by = FOLD_THREADS / bx;
+        const int rows = g.B[1] * g.B[2];
+        k_fold<<<dim3(g.ntiles, (rows + by - 1) / by), dim3(bx, by), 0, pl->stream>>>(f);
         return hipGetLastError();
     }
     SpreadArgs a{};
