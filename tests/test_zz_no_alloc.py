@@ -1,7 +1,8 @@
 """GPU: the allocation-free one-shot call (pppm_compute_noalloc) through the
 C ABI against pppm_compute on a regular plan, on the same inputs: two calls
 in a row on one GPU, the second with a smaller system (the static scratch
-keeps the first call's contents), in the mixed and FP64 forms, ad and ik;
+keeps the first call's contents), in the mixed and FP64 forms, ad and ik,
+at P = 5 and 7 (the two forms of make_rho);
 and the refusals (a request larger than the scratch, a rocFFT mesh)."""
 import numpy as np
 import pytest
@@ -29,10 +30,13 @@ def plan_result(w, diff, prec, io, pos, q):
     return res
 
 
+@pytest.mark.parametrize("order", [5, 7])
 @pytest.mark.parametrize("diff", ["ad", "ik"])
 @pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
-def test_noalloc_matches_plan_twice(diff, prec, io):
-    w = W.config(2)  # 32,001 charges of water, 64^3, P = 5
+def test_noalloc_matches_plan_twice(diff, prec, io, order):
+    # 32,001 charges of water, 64^3; at P = 7 the mixed form's make_rho takes
+    # the push form, whose boxes are carved from the scratch too
+    w = W.config(2, order=order)
     pos_r, q_r = io_round(w.pos, w.q, io)
     params = pkg.make_params(w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, max_particles=w.n)
     for n in (w.n, 9000):
