@@ -139,7 +139,14 @@ pppm_status pppm_validate(const pppm_params *params);
 /* Create a plan: validates params, allocates device scratch, builds the
  * influence function and the transform tables or rocFFT plans.  hip_stream is
  * a hipStream_t (NULL = the default stream) on the current device.  On
- * success *out is a plan. */
+ * success *out is a plan.
+ * make_rho (Map-Charge, Section 3.1) runs in one of two forms with the same
+ * results to the fixed-point resolution: each mesh tile pulling the charges
+ * whose stencils reach it, or, in the mixed precision at P = 7, each tile
+ * pushing its own charges' whole stencils into an extended box that a
+ * second kernel folds into the mesh.  PPPM_SPREAD=visit or =push in the
+ * environment when the plan is created forces one form (push only in the
+ * mixed precision and where its box fits the device's LDS). */
 pppm_status pppm_plan_create(const pppm_params *params, void *hip_stream, pppm_plan *out);
 
 /* Release a plan and all its device memory.  Synchronises its stream first.
