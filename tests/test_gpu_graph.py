@@ -19,11 +19,12 @@ import paper_1702_04250_amd as pkg  # noqa: E402
 DEV = torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("diff,prec,io", [("ad", "mixed", torch.float32), ("ik", "mixed", torch.float32),
-                                          ("ad", "fp64", torch.float64)])
-def test_graph_replays_match_eager(diff, prec, io):
-    w = W.config(2)
-    print(f"case graph replay C2 {diff} {prec}", flush=True)
+@pytest.mark.parametrize("diff,prec,io,order", [("ad", "mixed", torch.float32, 5), ("ik", "mixed", torch.float32, 5),
+                                                ("ad", "fp64", torch.float64, 5), ("ad", "mixed", torch.float32, 7)])
+def test_graph_replays_match_eager(diff, prec, io, order):
+    # at P = 7 the mixed form's make_rho is the push form (two kernels)
+    w = W.config(2, order=order)
+    print(f"case graph replay C2 {diff} {prec} P={order}", flush=True)
     stream = torch.cuda.Stream(device=DEV)
     plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, w.n, stream=stream)
     pos = torch.tensor(w.pos, dtype=io, device=DEV).contiguous()

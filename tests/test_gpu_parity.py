@@ -405,16 +405,18 @@ def test_mesh_charge_independent_of_particle_order(prec, io):
     plan.close()
 
 
+@pytest.mark.parametrize("order", [5, 7])
 @pytest.mark.parametrize("T", [500, 5000])
 @pytest.mark.parametrize("prec,io", [("mixed", torch.float32), ("fp64", torch.float64)])
 @pytest.mark.parametrize("diff", ["ad", "ik"])
-def test_weight_table_variant(T, prec, io, diff):
+def test_weight_table_variant(T, prec, io, diff, order):
     # the tabulated stencil weights against the oracle's tabulated variant
-    w = W.config(2)
+    # (at P = 7 the mixed form's make_rho takes its push form)
+    w = W.config(2, order=order)
     pos_r, q_r = io_round(w.pos, w.q, io)
     plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, prec, io, w.n,
                      weight_table=T)
-    print(f"case weight table T={T} {diff} {prec} io={io}", flush=True)
+    print(f"case weight table T={T} {diff} {prec} io={io} P={order}", flush=True)
     gpu = gpu_run(plan, pos_r, q_r, io)
     plan.close()
     ref = oracle.pppm(pos_r, q_r, w.box_lo, w.box_len, w.mesh, w.order, w.g_ewald, 1.0, diff, table=T)
