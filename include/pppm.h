@@ -245,8 +245,10 @@ const char *pppm_last_error(pppm_plan plan);
  * mapped particles (call pppm_particle_map or pppm_compute again).  Every
  * tile must be at least order - 1 points thick along an axis that has more
  * than one tile.  threads = workgroup size of the kernel `which`, a multiple
- * of 64: 0 = spread (64..1024), 1 = gather, forward (64..512), 2 = gather,
- * adjoint (64..512).
+ * of 64: 0 = spread (64..1024), 1 = gather, forward (64..512; the mixed ik
+ * gather 64..1024, by default 768 where the tile's LDS allows), 2 = gather,
+ * adjoint (64..512).  A new tile that leaves no room for the forward
+ * gather's workgroup narrows it to the widest that fits.
  * Returns PPPM_ERR_ARG (and changes nothing) for an unusable geometry,
  * including one whose shared memory exceeds the device limit. */
 pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t *tile, int32_t threads);

@@ -50,8 +50,16 @@ template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
 template <> struct Vec16<double> { using T = double2; };
 
+// Largest workgroup of a gather: 1024 threads for the mixed ik gather (its
+// three staged meshes leave one workgroup per CU, so a wider one keeps more
+// wavefronts in flight), 512 otherwise.  The plan's limits follow these.
+__host__ __device__ constexpr int gather_threads_max(int mode, int real_bytes)
+{
+    return (mode == GATHER_IK && real_bytes == 4) ? 1024 : 512;
+}
+
 template <int P, int MODE, typename R, typename TO, bool TAB>
-__global__ __launch_bounds__(512) void k_gather(GatherArgs a)
+__global__ __launch_bounds__(gather_threads_max(MODE, sizeof(R))) void k_gather(GatherArgs a)
 {
     constexpr int NC = (MODE == GATHER_IK) ? 3 : 1;
     constexpr bool DERIV = (MODE != GATHER_IK);
@@ -391,11 +399,11 @@ static size_t gather_sort_lds_bytes(int threads, size_t elem_bytes)
     return (size_t)threads * per + 64 * sizeof(int);
 }
 
-// Total LDS of a gather launch at the largest workgroup (512 threads): the
-// staged meshes plus the lane-assignment buffers.
-size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes)
+// Total LDS of a gather launch of `threads` threads: the staged meshes plus
+// the lane-assignment buffers.
+size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes, int threads)
 {
-    return gather_field_lds_bytes(g, order, ncomp, elem_bytes) + gather_sort_lds_bytes(512, elem_bytes);
+    return gather_field_lds_bytes(g, order, ncomp, elem_bytes) + gather_sort_lds_bytes(threads, elem_bytes);
 }
 
 hipError_t launch_gather(pppm_plan_s* pl, int mode, void* out0, void* out1, const double* grad_energy)

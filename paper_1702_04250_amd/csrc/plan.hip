@@ -188,8 +188,8 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget, bool allo
     g.ntiles = g.ntile[0] * g.ntile[1] * g.ntile[2];
     g.bin_stride = use_hist_map(pl, (int64_t)g.ntiles * NCLASS) ? 1 : NSUB;
     const size_t lds_s = spread_lds_bytes(g);
-    const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize);
-    const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize);
+    const size_t lds_g = gather_lds_bytes(g, P, pl->ncomp, pl->rsize, 512);
+    const size_t lds_a = gather_lds_bytes(g, P, 1, pl->rsize, 512);
     const size_t lim = pl->lds_limit - LDS_STATIC < lds_budget ? pl->lds_limit - LDS_STATIC : lds_budget;
     if ((int64_t)g.ntiles * NCLASS > pl->max_bins) return "tile too fine for the plan's bin arrays";
     if (lds_s > lim || lds_g > lim || lds_a > lim)
@@ -212,6 +212,27 @@ std::string set_tile(pppm_plan_s* pl, const int* B, size_t lds_budget, bool allo
     pl->nbins = (int64_t)g.ntiles * NCLASS;
     pl->stage = Stage::Empty;
     return "";
+}
+
+// Workgroup of the forward gather on the plan's tile: `want` threads or, when
+// the tile's staged meshes and lane buffers would not fit the LDS with them,
+// the most (a multiple of 64) that fit; a usable tile fits 512.
+int fit_gather_threads(const pppm_plan_s* pl, int want)
+{
+    int t = want;
+    while (t > 512 && gather_lds_bytes(pl->geo, pl->p.order, pl->ncomp, pl->rsize, t) + LDS_STATIC > pl->lds_limit)
+        t -= 64;
+    return t;
+}
+
+// Default forward-gather workgroup: 768 threads for the mixed ik gather (its
+// three staged meshes leave one workgroup per CU; measured on 524,288
+// charges at 128^3: 44.9 against 46.7 us at P = 5 and 94 against 112 us at
+// P = 7 for 512 threads, 1024 threads 44.5 and 107 us), where the LDS allows;
+// 512 for the others.
+int default_gather_threads(const pppm_plan_s* pl)
+{
+    return (pl->mixed && pl->p.diff == PPPM_DIFF_IK) ? fit_gather_threads(pl, 768) : 512;
 }
 
 // Default tile: the first usable shape of a preference list, each axis split
@@ -251,7 +272,10 @@ std::string default_tile(pppm_plan_s* pl, bool alloc = true)
                 continue;
             }
             why = set_tile(pl, B, budget, alloc);
-            if (why.empty()) return "";
+            if (why.empty()) {
+                pl->gather_cfg.threads = default_gather_threads(pl);
+                return "";
+            }
         }
     }
     return why;
@@ -841,10 +865,21 @@ pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t* t
     pppm_status st = check_plan(plan);
     if (st != PPPM_OK) return st;
     if (which < 0 || which > 2 || !tile) return fail(plan, PPPM_ERR_ARG, "which must be 0, 1 or 2 and tile non-NULL");
-    const int max_threads = which == 0 ? 1024 : 512;  // the kernels' launch bounds
+    // the kernels' launch bounds
+    const bool wide_gather = which == 1 && plan->mixed && plan->p.diff == PPPM_DIFF_IK;
+    const int max_threads = (which == 0 || wide_gather) ? 1024 : 512;
     if (threads < 64 || threads > max_threads || threads % 64)
         return fail(plan, PPPM_ERR_ARG, "threads must be a multiple of 64 in [64, " + std::to_string(max_threads) +
-                                            "] (1024 for make_rho, 512 for the gathers)");
+                                            "] (1024 for make_rho and the mixed ik gather, 512 for the other gathers)");
+    if (which == 1 && threads > 512) {
+        // the wider gather's lane buffers on the requested tile, checked
+        // before anything changes
+        MapGeo tg = plan->geo;
+        for (int d = 0; d < 3; ++d) tg.B[d] = tile[d] < tg.K[d] ? tile[d] : tg.K[d];
+        if (gather_lds_bytes(tg, plan->p.order, plan->ncomp, plan->rsize, threads) + LDS_STATIC > plan->lds_limit)
+            return fail(plan, PPPM_ERR_ARG,
+                        "a gather of " + std::to_string(threads) + " threads needs more LDS than the device has");
+    }
     const MapGeo keep = plan->geo;
     const int64_t keep_bins = plan->nbins;
     const Stage keep_stage = plan->stage;
@@ -859,6 +894,8 @@ pppm_status pppm_plan_set_launch(pppm_plan plan, int32_t which, const int32_t* t
         }
     }
     (which == 0 ? plan->spread_cfg : (which == 1 ? plan->gather_cfg : plan->adjoint_cfg)).threads = threads;
+    // a new tile may not leave room for the forward gather's workgroup
+    if (which != 1) plan->gather_cfg.threads = fit_gather_threads(plan, plan->gather_cfg.threads);
     return PPPM_OK;
 }
 

@@ -168,7 +168,7 @@ hipError_t launch_own_poisson(pppm_plan_s* pl, bool phi_only, double* energy_out
 size_t spread_lds_bytes(const MapGeo& g);
 size_t spread_push_lds_bytes(const MapGeo& g);
 int64_t spread_box_points(const MapGeo& g);
-size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
+size_t gather_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes, int threads);
 size_t gather_field_lds_bytes(const MapGeo& g, int order, int ncomp, size_t elem_bytes);
 
 enum GatherMode { GATHER_IK = 0, GATHER_AD = 1, GATHER_ADJOINT = 2 };

@@ -366,6 +366,52 @@ def test_gather_workgroup_limit():
     plan.close()
 
 
+def test_mixed_ik_gather_width():
+    # the mixed ik gather takes up to 1024 threads (768 by default where the
+    # LDS allows), the same forces at every width
+    w = W.config(1)
+    pos_r, q_r = io_round(w.pos, w.q, torch.float32)
+    ref = oracle_run(pos_r, q_r, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ik")
+    plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 5, w.g_ewald, 1.0, "ik", "mixed", torch.float32, w.n)
+    tile, threads = plan.get_launch(1)
+    assert threads == 768
+    forces = {}
+    for t in (768, 1024, 512):
+        plan.set_launch(1, tile, t)
+        print(f"case mixed ik gather {t} threads", flush=True)
+        gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+        errs, bad = compare(gpu, ref, "mixed")
+        assert not bad, bad
+        forces[t] = gpu["forces"]
+    assert np.array_equal(forces[768], forces[1024]) and np.array_equal(forces[768], forces[512])
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.set_launch(1, tile, 1088)
+    assert ei.value.status == -1
+    plan.close()
+    # a tile whose three staged meshes leave no room for 1024 threads' lane
+    # buffers (P = 7, 32 x 16 x 9: 150 KB of meshes): that width is refused
+    # and the plan keeps its geometry; 512 threads take the tile
+    lo, length, mesh = (0.0, 0.0, 0.0), (30.0, 30.0, 17.0), (64, 64, 36)
+    pos, q = W.random_system(2000, length, seed=4, box_lo=lo)
+    plan = make_plan(pkg, lo, length, mesh, 7, 0.45, 1.0, "ik", "mixed", torch.float32, 2000)
+    before = (plan.get_launch(0), plan.get_launch(1))
+    with pytest.raises(pkg.PPPMError) as ei:
+        plan.set_launch(1, (32, 16, 9), 1024)
+    assert ei.value.status == -1 and "LDS" in str(ei.value)
+    assert (plan.get_launch(0), plan.get_launch(1)) == before
+    # 768 threads on a smaller tile (96 KB of meshes), then make_rho moves
+    # the shared tile to 32 x 16 x 9: the gather narrows to a width that fits
+    plan.set_launch(1, (32, 8, 9), 768)
+    plan.set_launch(0, (32, 16, 9), 1024)
+    assert plan.get_launch(1)[0] == (32, 16, 9) and 512 <= plan.get_launch(1)[1] < 768
+    pos_r, q_r = io_round(pos, q, torch.float32)
+    print("case mixed ik gather after tile changes", flush=True)
+    gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+    errs, bad = compare(gpu, oracle_run(pos_r, q_r, lo, length, mesh, 7, 0.45, 1.0, "ik"), "mixed")
+    assert not bad, bad
+    plan.close()
+
+
 def test_tile_finer_than_bin_arrays_is_refused():
     w = W.config(3, order=2)
     plan = make_plan(pkg, w.box_lo, w.box_len, w.mesh, 2, w.g_ewald, 1.0, "ad", "mixed", torch.float32, 16)
