@@ -539,8 +539,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_inv(const Cplx<R>* __rest
 // chip.  In the odd half the partner of coefficient j in the symmetry above
 // is H - 1 - j (index -(2j+1) = 2(H-1-j)+1 mod K_y), in the even half
 // (H - j) mod H.
+// Both forms run 1024-thread blocks: a split pass has one block per CU on
+// the meshes that take it, and the pass is bound by the latency of its
+// load, exchange and store phases, which more wavefronts per CU hide (on
+// 128^3: 512-thread split blocks 35.8 us for the Poisson step, 1024-thread
+// 31.7 us, 256-thread 48.5 us).
 constexpr int XY_THREADS = 1024;
-constexpr int XY_HALF_THREADS = 512;
+constexpr int XY_HALF_THREADS = 1024;
 
 // Block b of a split pass over nb = 2 * planes blocks: blocks b and b + 8
 // take the two halves of one plane, so both run on one XCD and its L2

@@ -43,8 +43,23 @@ struct GatherArgs {
     const double* sfc;   // ad self-force coefficients of the stencil fraction's sines, or null
 };
 
-__device__ __forceinline__ float sin_pi(float x) { return sinpif(x); }
-__device__ __forceinline__ double sin_pi(double x) { return sinpi(x); }
+// sin(2 pi x).  FP32: the hardware sine, whose argument is in turns
+// (v_sin_f32, absolute error near 1e-6 for |x| < 2, far below what the small
+// ad self-force term needs); FP64: sinpi.
+__device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ double sin_turns(double x) { return sinpi(2.0 * x); }
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
@@ -191,6 +206,18 @@ __global__ __launch_bounds__(gather_threads_max(MODE, sizeof(R))) void k_gather(
     int* khist = sperm + blockDim.x;           // [64] bank histogram, then its prefix
     constexpr int KEYS = sizeof(R) == 4 ? 64 : 32;  // banks spanned by distinct starts
 
+    // ad self-force coefficients, loaded once; uniform, so they are kept in
+    // scalar registers
+    R sf1[3] = {R(0), R(0), R(0)}, sf2[3] = {R(0), R(0), R(0)};
+    const bool self_force = MODE == GATHER_AD && a.sfc != nullptr;
+    if (self_force) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            sf1[d] = uniform((R)a.sfc[d]);
+            sf2[d] = uniform((R)a.sfc[3 + d]);
+        }
+    }
+
     int l[3] = {0, 0, 0};
     R w[3][P], dw[3][P];
     for (int c0 = first; c0 < last; c0 += blockDim.x) {
@@ -316,7 +343,7 @@ __global__ __launch_bounds__(gather_threads_max(MODE, sizeof(R))) void k_gather(
                 out[3 * (size_t)iu + 2] = (TO)(qv * o2);
             } else if (MODE == GATHER_AD) {
                 R fo[3] = {-qv * o0 * (R)a.inv_h[0], -qv * o1 * (R)a.inv_h[1], -qv * o2 * (R)a.inv_h[2]};
-                if (a.sfc) {
+                if (self_force) {
                     // self-force q^2 (c1_d sin(2 pi f_d) + c2_d sin(4 pi f_d)) with f_d the
                     // stencil fraction (re-read from the record); c1 carries the sign
                     // that turns sin(2 pi f) into sin(2 pi u) for odd orders
@@ -326,7 +353,7 @@ __global__ __launch_bounds__(gather_threads_max(MODE, sizeof(R))) void k_gather(
                         int sd;
                         R f;
                         decode_local<R>(tt[d], ext[d], sd, f);
-                        fo[d] -= qv * qv * ((R)a.sfc[d] * sin_pi(R(2) * f) + (R)a.sfc[3 + d] * sin_pi(R(4) * f));
+                        fo[d] -= qv * qv * (sf1[d] * sin_turns(f) + sf2[d] * sin_turns(R(2) * f));
                     }
                 }
                 out[3 * (size_t)iu + 0] = (TO)fo[0];
