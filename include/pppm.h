@@ -142,11 +142,13 @@ pppm_status pppm_validate(const pppm_params *params);
  * success *out is a plan.
  * make_rho (Map-Charge, Section 3.1) runs in one of two forms with the same
  * results to the fixed-point resolution: each mesh tile pulling the charges
- * whose stencils reach it, or, in the mixed precision at P = 7, each tile
- * pushing its own charges' whole stencils into an extended box that a
- * second kernel folds into the mesh.  PPPM_SPREAD=visit or =push in the
- * environment when the plan is created forces one form (push only in the
- * mixed precision and where its box fits the device's LDS). */
+ * whose stencils reach it, or, in the mixed precision, each tile pushing its
+ * own charges' whole stencils into an extended box that a second kernel
+ * folds into the mesh.  The mixed precision takes the push form at P >= 6,
+ * and at P = 5 when there are fewer mesh tiles than compute units.
+ * PPPM_SPREAD=visit or =push in the environment when the plan is
+ * created forces one form (push only in the mixed precision and where its
+ * box fits the device's LDS). */
 pppm_status pppm_plan_create(const pppm_params *params, void *hip_stream, pppm_plan *out);
 
 /* Release a plan and all its device memory.  Synchronises its stream first.

@@ -138,12 +138,18 @@ void host_weights(int P, double f, double* w, double* dw)
     }
 }
 
-// make_rho's form for tile geometry g, in the mixed form: the push form
-// (k_spread_push + k_fold) at P = 7, where the halo pulls of the
-// owner-computes form double its time (measured on the default tile: 82 vs
-// 88 us on 524,288 charges at 128^3, 692 vs 760 us on 4.2M charges at
-// 256^3; at P = 6 the two are even, at P = 5 the owner-computes form is
-// faster, 37 vs 27 + 16.5 us for the push kernel and its fold).
+// make_rho's form for tile geometry g, in the mixed form.  The push form
+// (k_spread_push + k_fold) issues about half the LDS atomics of the
+// owner-computes form (no halo pulls, no clipped rows) and pays a second
+// pass over the boxes.  Measured on the default tiles (make_rho, us, owner-
+// computes against push): P = 7: 89 / 77 on 524,288 charges at 128^3;
+// P = 6: 57.5 / 53 there, 499 / 412 on 4.2M charges at 256^3, 32 / 25.5 on
+// 65,536 charges at 64^3; P = 5: 37.1 / 39.8 at 128^3 (512 tiles), 48.8 /
+// 58.4 at 160^3 (1,000 tiles), but 21.4 / 18.5 at 64^3 with 64 tiles, where
+// the owner-computes form's doubled atomics sit on a quarter of the CUs and
+// the push form moves that work into a fold that spreads over all of them
+// (and 331 / 293 at 256^3, 4,096 tiles); P = 4: 24.9 / 31.9 at 128^3.  So the
+// push form at P >= 6, and at P = 5 when there are fewer tiles than CUs.
 // PPPM_SPREAD=push takes the push form at any order, =visit never.  Only
 // when the box fits the LDS; with alloc the box buffer is grown here, and if
 // that fails the plan keeps to the owner-computes form.
@@ -151,7 +157,10 @@ void choose_spread_form(pppm_plan_s* pl, const MapGeo& g, bool alloc)
 {
     pl->spread_push = false;
     if (!pl->mixed || pl->spread_mode == 1) return;
-    if (pl->spread_mode == 0 && pl->p.order < 7) return;
+    if (pl->spread_mode == 0) {
+        const int P = pl->p.order;
+        if (P <= 4 || (P == 5 && g.ntiles >= pl->num_cu)) return;
+    }
     if (spread_push_lds_bytes(g) > pl->lds_limit - LDS_STATIC) return;
     if (alloc) {
         const size_t bytes = (size_t)g.ntiles * spread_box_points(g) * sizeof(float);
@@ -383,9 +392,13 @@ pppm_status init_plan_geometry(pppm_plan_s* pl, const pppm_params* params, void*
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
     if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
     pl->lds_limit = (size_t)lds;
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (e != hipSuccess) return fail(pl, PPPM_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
+    pl->num_cu = ncu > 0 ? ncu : 1;
     // PPPM_SPREAD=visit keeps make_rho to the owner-computes form, =push takes
     // the push form at every order whenever its box fits the LDS (for
-    // comparisons); otherwise the form follows the order
+    // comparisons); otherwise the form follows the order and the tile count
     const char* spread_env = std::getenv("PPPM_SPREAD");
     pl->spread_mode = !spread_env ? 0 : (std::strcmp(spread_env, "visit") == 0 ? 1 : (std::strcmp(spread_env, "push") == 0 ? 2 : 0));
 

@@ -66,6 +66,7 @@ struct pppm_plan_s {
     hipStream_t stream = nullptr;
     int device = 0;
     size_t lds_limit = 65536;
+    int num_cu = 256;          // compute units of the plan's device
 
     pppm::MapGeo geo{};
     int64_t ncell = 0;   // Kx Ky Kz

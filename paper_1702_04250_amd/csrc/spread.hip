@@ -10,9 +10,10 @@
 // coalesced stores: no global atomics and no zero-fill of the mesh.
 // This is the GPU counterpart of the paper's per-thread private grids
 // ("rethread"): privatise, accumulate, then combine - here the combine is a
-// disjoint ownership of the output.  At P = 7 the mixed form takes the push
-// form instead (k_spread_push + k_fold, below): each tile sums only its own
-// charges, whole stencils, and a fold kernel combines the overlapping tiles.
+// disjoint ownership of the output.  At P >= 6 (and at P = 5 when the tiles
+// are fewer than the CUs) the mixed form takes the push form instead
+// (k_spread_push + k_fold, below): each tile sums only its own charges,
+// whole stencils, and a fold kernel combines the overlapping tiles.
 //
 // Accumulator.  On gfx950 the LDS float atomic add (ds_add_f32) is processed
 // at about one lane every three clocks for any non-uniform address pattern,
@@ -621,15 +622,31 @@ __global__ __launch_bounds__(FOLD_THREADS) void k_fold(FoldArgs f)
         el[d] = tile_extent(g, d, tl[d]);
     }
     const int mask = (lx < H ? 1 : 0) | (ly < H ? 2 : 0) | (lz < H ? 4 : 0);
-    double sum = 0.0;
+    // The terms any lane of the wavefront needs (a uniform mask) are loaded
+    // first, all in flight together, then added in the fixed order; a lane
+    // that needs fewer terms reads its own point for the others and drops
+    // them.  (Loading and adding term by term waits out one memory round
+    // trip per term.)
+    const int wmask = (__any(mask & 1) ? 1 : 0) | (__any(mask & 2) ? 2 : 0) | (__any(mask & 4) ? 4 : 0);
+    const size_t own = (size_t)tile * f.stride + (size_t)(lz * f.rows + ly) * f.pitch + lx;
+    float v[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-        if ((m & mask) != m) continue;
-        const int sx = (m & 1) ? tl[0] : t[0], sy = (m & 2) ? tl[1] : t[1], sz = (m & 4) ? tl[2] : t[2];
-        const int cx = lx + ((m & 1) ? el[0] : 0), cy = ly + ((m & 2) ? el[1] : 0), cz = lz + ((m & 4) ? el[2] : 0);
-        const float* nb = f.box + (size_t)((sz * g.ntile[1] + sy) * g.ntile[0] + sx) * f.stride;
-        sum += (double)nb[(cz * f.rows + cy) * f.pitch + cx];
+        v[m] = 0.0f;
+        if ((m & wmask) != m) continue;
+        size_t idx = own;
+        if ((m & mask) == m) {
+            const int sx = (m & 1) ? tl[0] : t[0], sy = (m & 2) ? tl[1] : t[1], sz = (m & 4) ? tl[2] : t[2];
+            const int cx = lx + ((m & 1) ? el[0] : 0), cy = ly + ((m & 2) ? el[1] : 0),
+                      cz = lz + ((m & 4) ? el[2] : 0);
+            idx = (size_t)((sz * g.ntile[1] + sy) * g.ntile[0] + sx) * f.stride + (size_t)(cz * f.rows + cy) * f.pitch + cx;
+        }
+        v[m] = f.box[idx];
     }
+    double sum = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if ((m & mask) == m) sum += (double)v[m];
     const size_t gi = ((size_t)(t[2] * g.B[2] + lz) * g.K[1] + (t[1] * g.B[1] + ly)) * g.K[0] + (t[0] * g.B[0] + lx);
     f.rho[gi] = (float)sum;
     if (f.rho_user) f.rho_user[gi] = sum;

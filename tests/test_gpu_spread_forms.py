@@ -2,8 +2,9 @@
 same inputs: the owner-computes form (each tile pulls the charges whose
 stencils reach it) and the push form (each tile sums its own charges' whole
 stencils into a box extended by P - 1, then a fold adds the overlapping
-boxes).  The plan takes the push form at P = 7 by itself; PPPM_SPREAD forces
-either form at plan creation.  Cases: the benchmark system at P = 5 and 7,
+boxes).  The plan takes the push form at P >= 6 by itself, and at P = 5
+when there are fewer mesh tiles than CUs; PPPM_SPREAD forces either form at
+plan creation.  Cases: the benchmark system at P = 5 and 7,
 ragged meshes with axes of one tile (the boxes wrap onto the start of the
 axis), a dense cluster at P = 7 (64-bit box sums), and the mesh charge of
 the FP64 output (the fold also writes the caller's FP64 mesh)."""
@@ -96,18 +97,41 @@ def test_dense_cluster_in_both_forms():
         assert err <= 1e-4
 
 
-def test_push_form_is_the_default_at_order_7():
-    # no variable set: P = 7 takes the push form, P = 5 the owner-computes
-    # form; each matches the plan forced to that form bit for bit
-    w = W.config(1)
+def expected_form(plan, mesh, P):
+    # the plan's rule: the push form at P >= 6, and at P = 5 when there are
+    # fewer tiles than CUs; the owner-computes form otherwise
+    tile, _ = plan.get_launch(0)
+    ntiles = int(np.prod([-(-k // b) for k, b in zip(mesh, tile)]))
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    if P >= 6:
+        return "push"
+    if P == 5:
+        return "push" if ntiles < ncu else "visit"
+    return "visit"
+
+
+@pytest.mark.parametrize("idx,P", [(1, 7), (1, 6), (1, 5), (1, 4), (2, 5), (3, 5), (3, 6)])
+def test_default_form_of_make_rho(idx, P):
+    # no variable set: the plan's default form matches the plan forced to
+    # that form bit for bit
+    w = W.config(idx, order=P)
     pos_r, q_r = io_round(w.pos, w.q, torch.float32)
     assert "PPPM_SPREAD" not in os.environ
-    for P, form in ((7, "push"), (5, "visit")):
-        default = make_plan(pkg, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32, w.n)
-        forced = plan_in_form(form, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", w.n)
-        print(f"case default form at P={P}", flush=True)
-        a = gpu_run(default, pos_r, q_r, torch.float32)
-        b = gpu_run(forced, pos_r, q_r, torch.float32)
-        default.close()
-        forced.close()
-        assert np.array_equal(a["rho"], b["rho"]) and a["energy"] == b["energy"]
+    default = make_plan(pkg, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, 1.0, "ad", "mixed", torch.float32, w.n)
+    form = expected_form(default, w.mesh, P)
+    forced = plan_in_form(form, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", w.n)
+    other = plan_in_form("visit" if form == "push" else "push", w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", w.n)
+    print(f"case default form config {idx} P={P}: {form}", flush=True)
+    a = gpu_run(default, pos_r, q_r, torch.float32)
+    b = gpu_run(forced, pos_r, q_r, torch.float32)
+    c = gpu_run(other, pos_r, q_r, torch.float32)
+    for p in (default, forced, other):
+        p.close()
+    assert np.array_equal(a["rho"], b["rho"]) and a["energy"] == b["energy"]
+    same = np.array_equal(a["rho"], c["rho"])
+    print(f"  other form bitwise the same: {same}", flush=True)
+    if idx == 3:
+        # on the benchmark system the forms' exponents and FP32 box sums
+        # differ, so the bits tell them apart (on 1,000 charges they can
+        # coincide)
+        assert not same
