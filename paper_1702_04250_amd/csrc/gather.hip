@@ -43,9 +43,10 @@ struct GatherArgs {
     const double* sfc;   // ad self-force coefficients of the stencil fraction's sines, or null
 };
 
-// sin(2 pi x).  FP32: the hardware sine, whose argument is in turns
-// (v_sin_f32, absolute error near 1e-6 for |x| < 2, far below what the small
-// ad self-force term needs); FP64: sinpi.
+// sin(2 pi x) for x in [0, 2].  FP32: the hardware sine, whose argument is
+// in turns (v_sin_f32); the ad self-force term it serves is a small
+// correction, and on lone charges (whose force is all self-force) the
+// corrections it gives match the FP64 ones to about 2e-6.  FP64: sinpi.
 __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ double sin_turns(double x) { return sinpi(2.0 * x); }
 
