@@ -94,8 +94,9 @@ def _short(name):
     first 60 characters."""
     import re
 
-    m = re.search(r"\b(k_[A-Za-z0-9_]+)", name.split("(")[0])
-    return m.group(1) if m else name.split("(")[0][:60]
+    head = name.replace("(anonymous namespace)", "").split("(")[0]
+    m = re.search(r"\b(k_[A-Za-z0-9_]+)", head)
+    return m.group(1) if m else head[:60]
 
 
 def _matches(name, kernel_filter):
