@@ -193,7 +193,10 @@ pppm_status pppm_compute(pppm_plan plan, int64_t n, const void *pos, const void 
  * must start at zero is cleared by a kernel), so it can be captured.
  * The influence function and transform tables are rebuilt by every call (at
  * 128^3 they take about 0.1 ms).  Same arguments, layouts and results as
- * pppm_compute; hip_stream as in pppm_plan_create.
+ * pppm_compute; hip_stream as in pppm_plan_create.  Where a plan would take
+ * the push form of make_rho and its boxes do not fit the array beside the
+ * rest, the call takes the owner-computes form: its results then agree with
+ * pppm_compute to the fixed-point resolution rather than bit for bit.
  * Limits: the mesh must be one the library's own transforms take (see the
  * Poisson step above; rocFFT plans allocate), and neither
  * PPPM_FLAG_WEIGHT_TABLE nor PPPM_FLAG_CHECK_FINITE is taken; parameters that
