@@ -4,7 +4,7 @@ stencils reach it) and the push form (each tile sums its own charges' whole
 stencils into a box extended by P - 1, then a fold adds the overlapping
 boxes).  The plan takes the push form at P >= 6 by itself, and at P = 5
 when there are fewer mesh tiles than CUs; PPPM_SPREAD forces either form at
-plan creation.  Cases: the benchmark system at P = 5 and 7,
+plan creation.  Cases: the benchmark system at P = 5, 6 and 7,
 ragged meshes with axes of one tile (the boxes wrap onto the start of the
 axis), a dense cluster at P = 7 (64-bit box sums), and the mesh charge of
 the FP64 output (the fold also writes the caller's FP64 mesh)."""
@@ -63,7 +63,7 @@ def both_forms(pos, q, box_lo, box_len, mesh, P, g, diff, label, launch=None, st
     return out, ref
 
 
-@pytest.mark.parametrize("P", [5, 7])
+@pytest.mark.parametrize("P", [5, 6, 7])
 def test_benchmark_system_in_both_forms(P):
     w = W.config(3, order=P)
     both_forms(w.pos, w.q, w.box_lo, w.box_len, w.mesh, P, w.g_ewald, "ad", f"uniform 524k P={P}",
