@@ -1,0 +1,91 @@
+"""GPU: a seeded random sweep against the oracle.  Each case draws a mesh
+(library transforms and rocFFT sizes, 4 to 64 points per axis), an order P
+= 2..7, ad or ik, the mixed or FP64 form, either form of make_rho (or the
+plan's default), 1 to 4,000 charges with positions up to half a box outside
+it, unit or Gaussian charges (neutral or not), an Ewald split scaled to the
+mesh, sometimes a launch geometry set through pppm_plan_set_launch (refused
+ones keep the default), and sometimes the energy backward; results and
+gradients are checked to the same tolerances as the fixed cases.  A lone
+charge is not drawn in ik mode: its force is zero up to rounding, so it has
+no relative error."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import compare, gpu_run, io_round, make_plan, oracle_run, rms_rel
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1702_04250_amd as pkg  # noqa: E402
+
+SIZES = [4, 6, 8, 9, 10, 12, 14, 16, 18, 20, 24, 27, 30, 32, 36, 40, 48, 64]
+TOL_GRAD = {"fp64": 1e-10, "mixed": 1e-3}
+
+
+def draw(case):
+    rng = np.random.default_rng(20260 + case)
+    P = int(rng.integers(2, 8))
+    mesh = tuple(int(rng.choice([k for k in SIZES if k >= max(P, 2)])) for _ in range(3))
+    n = int(rng.choice([1, 7, 100, 1000, 4000]))
+    diff = str(rng.choice(["ad", "ik"]))
+    if diff == "ik" and n == 1:
+        n = 2
+    length = tuple(float(x) for x in rng.uniform(5.0, 30.0, size=3))
+    lo = tuple(float(x) for x in rng.uniform(-10, 10, size=3))
+    pos = np.asarray(lo) + rng.uniform(-0.5, 1.5, size=(n, 3)) * np.asarray(length)
+    q = rng.choice([-1.0, 1.0], size=n) if rng.random() < 0.5 else rng.normal(0, 1, size=n)
+    if rng.random() < 0.5 and n > 1:
+        q = q - q.mean()
+    h = min(length[d] / mesh[d] for d in range(3))
+    g = float(rng.uniform(0.8, 2.0) / (h * 4))
+    prec = str(rng.choice(["mixed", "fp64"]))
+    form = str(rng.choice(["default", "visit", "push"]))
+    launch = None
+    if rng.random() < 0.4:
+        launch = (tuple(int(rng.choice([4, 8, 12, 16, 32])) for _ in range(3)), int(rng.choice([256, 512, 1024])))
+    backward = n > 1 and rng.random() < 0.5
+    return P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, backward
+
+
+@pytest.mark.parametrize("case", range(48))
+def test_random_case_against_the_oracle(case):
+    P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, backward = draw(case)
+    io = torch.float32 if prec == "mixed" else torch.float64
+    print(f"case random {case}: P={P} mesh={mesh} n={n} {diff} {prec} form={form} launch={launch} "
+          f"backward={backward}", flush=True)
+    assert "PPPM_SPREAD" not in os.environ
+    if form != "default":
+        os.environ["PPPM_SPREAD"] = form
+    try:
+        plan = make_plan(pkg, lo, length, mesh, P, g, 1.0, diff, prec, io, n)
+    finally:
+        os.environ.pop("PPPM_SPREAD", None)
+    if launch:
+        try:
+            plan.set_launch(0, *launch)
+        except pkg.PPPMError:
+            print("  launch refused: default kept", flush=True)
+    pos_r, q_r = io_round(pos, q, io)
+    gpu = gpu_run(plan, pos_r, q_r, io)
+    ref = oracle_run(pos_r, q_r, lo, length, mesh, P, g, 1.0, diff)
+    errs, bad = compare(gpu, ref, prec)
+    if backward:
+        pt = torch.tensor(pos_r, dtype=io, device="cuda:0", requires_grad=True)
+        qt = torch.tensor(q_r, dtype=io, device="cuda:0", requires_grad=True)
+        pkg.pppm_energy(pt, qt, plan).backward()
+        torch.cuda.synchronize()
+        rg = oracle.energy_gradients(pos_r, q_r, lo, length, mesh, P, g, 1.0, diff)
+        errs["grad_pos"] = rms_rel(pt.grad.cpu().numpy().astype(np.float64), rg["grad_pos"])
+        errs["grad_q"] = rms_rel(qt.grad.cpu().numpy().astype(np.float64), rg["grad_q"])
+        for k in ("grad_pos", "grad_q"):
+            if not errs[k] <= TOL_GRAD[prec]:
+                bad[k] = errs[k]
+    plan.close()
+    print(f"  errors {errs}", flush=True)
+    assert not bad, bad
