@@ -7,7 +7,11 @@ mesh, sometimes a launch geometry set through pppm_plan_set_launch (refused
 ones keep the default), and sometimes the energy backward; results and
 gradients are checked to the same tolerances as the fixed cases.  A lone
 charge is not drawn in ik mode: its force is zero up to rounding, so it has
-no relative error."""
+no relative error.  A second set draws dense systems (20,000 to 60,000
+charges on meshes of 8 to 32 points per axis, most of them clustered
+within a few cells), which exercise the 64-bit sums of crowded tiles; their
+charges are unit or Gaussian (a range of |q| over several orders of
+magnitude at that density is outside the mixed form's bound)."""
 import os
 
 import numpy as np
@@ -53,11 +57,46 @@ def draw(case):
     return P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, backward
 
 
+def draw_dense(case):
+    rng = np.random.default_rng(40520 + case)
+    P = int(rng.integers(2, 8))
+    mesh = tuple(int(rng.choice([k for k in (8, 12, 16, 20, 24, 32) if k >= P])) for _ in range(3))
+    n = int(rng.choice([20000, 60000]))
+    diff = str(rng.choice(["ad", "ik"]))
+    length = tuple(float(x) for x in rng.uniform(5.0, 30.0, size=3))
+    lo = tuple(float(x) for x in rng.uniform(-10, 10, size=3))
+    pos = np.asarray(lo) + rng.uniform(0.0, 1.0, size=(n, 3)) * np.asarray(length)
+    if rng.random() < 0.6:
+        c0 = np.asarray(lo) + rng.uniform(0, 1, size=3) * np.asarray(length)
+        k = int(0.8 * n)
+        pos[:k] = c0 + rng.normal(0, 1, size=(k, 3)) * (0.05 * np.asarray(length))
+    q = rng.choice([-1.0, 1.0], size=n) if rng.random() < 0.5 else rng.normal(0, 1, size=n)
+    if rng.random() < 0.5:
+        q = q - q.mean()
+    h = min(length[d] / mesh[d] for d in range(3))
+    g = float(rng.uniform(0.8, 2.0) / (h * 4))
+    prec = str(rng.choice(["mixed", "fp64"]))
+    form = str(rng.choice(["default", "visit", "push"]))
+    launch = None
+    if rng.random() < 0.4:
+        launch = (tuple(int(rng.choice([4, 8, 12, 16, 32])) for _ in range(3)), int(rng.choice([256, 512, 1024])))
+    return P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, False
+
+
 @pytest.mark.parametrize("case", range(48))
 def test_random_case_against_the_oracle(case):
-    P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, backward = draw(case)
+    run_case(f"random {case}", draw(case))
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_dense_case_against_the_oracle(case):
+    run_case(f"dense random {case}", draw_dense(case))
+
+
+def run_case(label, drawn):
+    P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, backward = drawn
     io = torch.float32 if prec == "mixed" else torch.float64
-    print(f"case random {case}: P={P} mesh={mesh} n={n} {diff} {prec} form={form} launch={launch} "
+    print(f"case {label}: P={P} mesh={mesh} n={n} {diff} {prec} form={form} launch={launch} "
           f"backward={backward}", flush=True)
     assert "PPPM_SPREAD" not in os.environ
     if form != "default":
