@@ -13,7 +13,7 @@ struct EnergySums {
     const double* qpart;
     double self_c;           // C g / sqrt(pi)
     double bg_c;             // C pi / (2 V g^2)
-    double* eterms;          // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, ...
+    double* eterms;          // [10] E, E_mesh, E_self, E_bg, Q, sum q^2, ...
     double* energy_out;      // caller's energy or null
 };
 

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(PREFIX_THREADS) void k_hist_prefix(int nbins, int n
 
 // Single-workgroup exclusive scan of the bin totals (nbins <= HIST_MAX_BINS)
 // into offsets[0 .. nbins]; zeroes count again; stats[0] = largest bin,
-// stats[1] = max |q| from the count pass's partials.
+// stats[1] = max |q| and stats[2] = sum q^2 from the count pass's partials.
 constexpr int SSCAN_THREADS = 1024;
 constexpr int SSCAN_PER = HIST_MAX_BINS / SSCAN_THREADS;
 
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(SSCAN_THREADS) void k_scan_single(int nbins, int* _
                                                                 double* __restrict__ stats)
 {
     __shared__ int scratch[17];
-    __shared__ double smax[2][SSCAN_THREADS / 64];
+    __shared__ double smax[3][SSCAN_THREADS / 64];
     const int per = (nbins + SSCAN_THREADS - 1) / SSCAN_THREADS;  // <= SSCAN_PER
     const int j0 = threadIdx.x * per;
     int c[SSCAN_PER];
@@ -225,27 +225,34 @@ __global__ __launch_bounds__(SSCAN_THREADS) void k_scan_single(int nbins, int* _
             ex += c[u];
             count[j0 + u] = 0;
         }
-    double mq = 0.0;
-    for (int j = threadIdx.x; j < nqblocks; j += SSCAN_THREADS) mq = fmax(mq, qpart[3 * j + 2]);
+    double mq = 0.0, sq = 0.0;
+    for (int j = threadIdx.x; j < nqblocks; j += SSCAN_THREADS) {
+        mq = fmax(mq, qpart[3 * j + 2]);
+        sq += qpart[3 * j + 1];
+    }
     double mcd = (double)mc;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
         mcd = fmax(mcd, __shfl_down(mcd, d, 64));
         mq = fmax(mq, __shfl_down(mq, d, 64));
+        sq += __shfl_down(sq, d, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         smax[0][threadIdx.x >> 6] = mcd;
         smax[1][threadIdx.x >> 6] = mq;
+        smax[2][threadIdx.x >> 6] = sq;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double x = 0.0, y = 0.0;
+        double x = 0.0, y = 0.0, z = 0.0;
         for (int w = 0; w < SSCAN_THREADS / 64; ++w) {
             x = fmax(x, smax[0][w]);
             y = fmax(y, smax[1][w]);
+            z += smax[2][w];
         }
         stats[0] = x;
         stats[1] = y;
+        stats[2] = z;
         offsets[nbins] = total;
     }
 }
@@ -281,7 +288,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(int nbins_, int nb
 
 // Exclusive prefix of the counts -> offsets; counts are reset to zero for the
 // next call.  offsets[nbins] = number of particles.  Block 0 also writes
-// stats[0] = largest (sub-)bin count and stats[1] = max |q| (from the
+// stats[0] = largest (sub-)bin count, stats[1] = max |q| and stats[2] =
+// sum q^2 (from the
 // particle-map partials); max |q| bounds the mesh charge of any point.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nblocks, int* __restrict__ count,
                                                               const int* __restrict__ part,
@@ -291,30 +299,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nbl
 {
     __shared__ int scratch[17];
     __shared__ int sbase;
-    __shared__ double smax[2][SCAN_THREADS / 64];
+    __shared__ double smax[3][SCAN_THREADS / 64];
     if (blockIdx.x == 0) {
         int mc = 0;
-        double mq = 0.0;
+        double mq = 0.0, sq = 0.0;
         for (int j = threadIdx.x; j < nblocks; j += SCAN_THREADS) mc = max(mc, part[nblocks + j]);
-        for (int j = threadIdx.x; j < nqblocks; j += SCAN_THREADS) mq = fmax(mq, qpart[3 * j + 2]);
+        for (int j = threadIdx.x; j < nqblocks; j += SCAN_THREADS) {
+            mq = fmax(mq, qpart[3 * j + 2]);
+            sq += qpart[3 * j + 1];
+        }
         double mcd = (double)mc;
         for (int d = 32; d > 0; d >>= 1) {
             mcd = fmax(mcd, __shfl_down(mcd, d, 64));
             mq = fmax(mq, __shfl_down(mq, d, 64));
+            sq += __shfl_down(sq, d, 64);
         }
         if ((threadIdx.x & 63) == 0) {
             smax[0][threadIdx.x >> 6] = mcd;
             smax[1][threadIdx.x >> 6] = mq;
+            smax[2][threadIdx.x >> 6] = sq;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double a = 0.0, b = 0.0;
+            double a = 0.0, b = 0.0, c = 0.0;
             for (int w = 0; w < SCAN_THREADS / 64; ++w) {
                 a = fmax(a, smax[0][w]);
                 b = fmax(b, smax[1][w]);
+                c += smax[2][w];
             }
             stats[0] = a;
             stats[1] = b;
+            stats[2] = c;
         }
     }
     // base of this chunk: sum of the chunks before it
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_scatter_scan(int n, int chunk,
 {
     extern __shared__ int loff[];  // [nbins] exclusive prefix of the bin totals
     __shared__ int scratch[17];
-    __shared__ double smax[2][HIST_THREADS / 64];
+    __shared__ double smax[3][HIST_THREADS / 64];
     constexpr int PER = FUSED_SCAN_MAX_BINS / HIST_THREADS;
     const int per = (nbins + HIST_THREADS - 1) / HIST_THREADS;  // <= PER
     const int j0 = threadIdx.x * per;
@@ -449,27 +464,34 @@ __global__ __launch_bounds__(HIST_THREADS) void k_scatter_scan(int n, int chunk,
         }
     if (pub) {
         // largest bin and largest |q| (from the count pass's partials)
-        double mq = 0.0;
-        for (int j = threadIdx.x; j < nqblocks; j += HIST_THREADS) mq = fmax(mq, qpart[3 * j + 2]);
+        double mq = 0.0, sq = 0.0;
+        for (int j = threadIdx.x; j < nqblocks; j += HIST_THREADS) {
+            mq = fmax(mq, qpart[3 * j + 2]);
+            sq += qpart[3 * j + 1];
+        }
         double mcd = (double)mc;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) {
             mcd = fmax(mcd, __shfl_down(mcd, d, 64));
             mq = fmax(mq, __shfl_down(mq, d, 64));
+            sq += __shfl_down(sq, d, 64);
         }
         if ((threadIdx.x & 63) == 0) {
             smax[0][threadIdx.x >> 6] = mcd;
             smax[1][threadIdx.x >> 6] = mq;
+            smax[2][threadIdx.x >> 6] = sq;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double x = 0.0, y = 0.0;
+            double x = 0.0, y = 0.0, z = 0.0;
             for (int w = 0; w < HIST_THREADS / 64; ++w) {
                 x = fmax(x, smax[0][w]);
                 y = fmax(y, smax[1][w]);
+                z += smax[2][w];
             }
             stats[0] = x;
             stats[1] = y;
+            stats[2] = z;
             offsets[nbins] = total;
         }
     }

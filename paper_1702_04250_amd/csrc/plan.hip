@@ -611,12 +611,12 @@ pppm_status pppm_plan_create(const pppm_params* params, void* hip_stream, pppm_p
         (st = dmalloc(pl, &pl->field, z.field)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->G, z.G)) != PPPM_OK ||
         (st = dmalloc(pl, &pl->epart, z.epart)) != PPPM_OK ||
-        (st = dmalloc(pl, &pl->eterms, 8 * sizeof(double))) != PPPM_OK ||
+        (st = dmalloc(pl, &pl->eterms, 10 * sizeof(double))) != PPPM_OK ||
         (st = dmalloc(pl, &pl->flags, sizeof(int))) != PPPM_OK)
         return bail(st);
 
     e = hipMemsetAsync(pl->flags, 0, sizeof(int), pl->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 8 * sizeof(double), pl->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->eterms, 0, 10 * sizeof(double), pl->stream);
     if (e != hipSuccess) {
         pl->last_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
         return bail(PPPM_ERR_HIP);
@@ -787,7 +787,7 @@ pppm_status pppm_compute_noalloc(const pppm_params* params, void* hip_stream, in
     c.take(&pl.field, z.field);
     c.take(&pl.G, z.G);
     c.take(&pl.epart, z.epart);
-    c.take(&pl.eterms, 8 * sizeof(double));
+    c.take(&pl.eterms, 10 * sizeof(double));
     c.take(&pl.flags, sizeof(int));
     c.take(&pl.fft_tw, z.fft_tw);
     if (params->flags & PPPM_FLAG_AD_SELF_FORCE) c.take(&pl.sfc, z.sfc);
@@ -812,7 +812,7 @@ pppm_status pppm_compute_noalloc(const pppm_params* params, void* hip_stream, in
     // What must start at zero: the energy terms, the sticky flag and (for the
     // atomic form of the particle map) the bin counters.  The array keeps
     // the contents of the last call on this GPU.
-    k_zero_words<<<1, 64, 0, pl.stream>>>((unsigned*)pl.eterms, 16);
+    k_zero_words<<<1, 64, 0, pl.stream>>>((unsigned*)pl.eterms, 20);
     k_zero_words<<<1, 64, 0, pl.stream>>>((unsigned*)pl.flags, 1);
     if (pl.geo.bin_stride != 1)
         k_zero_words<<<(unsigned)std::min<int64_t>((nent + 255) / 256, 1024), 256, 0, pl.stream>>>(

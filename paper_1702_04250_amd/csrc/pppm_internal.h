@@ -98,7 +98,8 @@ struct pppm_plan_s {
     void* field = nullptr;     // [(ncomp + 1) * ncell] R: field meshes, then phi (ik adjoint)
     double* G = nullptr;       // [nspec] (C / V) G(k); own transforms: [Kz/2+1][Ky/2+1][Kx/2+1] octant
     double* epart = nullptr;   // [kspace blocks] partial sums of the mesh energy
-    double* eterms = nullptr;  // [8] E, E_mesh, E_self, E_bg, Q, sum q^2, max count, max |q|
+    double* eterms = nullptr;  // [10] E, E_mesh, E_self, E_bg, Q, sum q^2, then from the particle map:
+                               // max count, max |q|, sum q^2, unused
     void* wtab = nullptr;      // stencil-weight table (PPPM_FLAG_WEIGHT_TABLE)
     double* sfc = nullptr;     // (PPPM_FLAG_AD_SELF_FORCE) [6 + 6 * kspace blocks]: per axis
                                // (-1)^P 2 pi S1_d / h_d, then 4 pi S2_d / h_d (factors of the sines

@@ -33,7 +33,9 @@
 // finer than bounding by all the charges the tile reads.  A tile that reads
 // more than WIDE_VISITS charges (a dense cluster) skips the count and sums
 // the same 32-bit rounded contributions in 64 bits (ds_add_u64), with the
-// unit set by the largest single contribution.
+// unit set by the largest single contribution; so does a tile whose reach
+// bound exceeds WIDE_REACH, and every tile when the largest |q| exceeds
+// WIDE_RANGE times the RMS |q| of all the charges.
 // The rounding is unbiased: each contribution v is rounded to floor(v + d)
 // with a dither d in [0, 1) that is a hash of the charge's record and of the
 // stencil point, so its expectation is v.  Rounding to nearest instead sends
@@ -66,7 +68,7 @@ struct SpreadArgs {
     const void* rec;
     void* rho;            // plan mesh of type R (the FFT input)
     double* rho_user;     // caller's FP64 mesh or null
-    const double* stats;  // [1] max |q|
+    const double* stats;  // [1] max |q|, [2] sum q^2 (from the particle map)
     int pitch_x;          // LDS row pitch (points): B_x + 2 (P - 1)
     int rows_y;           // LDS rows per plane: B_y, + P - 1 on a single-tile axis
     int planes_z;         // LDS planes: B_z, + P - 1 on a single-tile axis
@@ -109,6 +111,24 @@ __device__ __forceinline__ int fixed_point_exponent(int visits, double qmax)
 // exponent only has to keep one contribution (a 32-bit integer) below 2^30
 // units; the sum of at most 2^31 of them stays far inside 2^63.
 constexpr int WIDE_VISITS = 8192;
+// ... and so does every tile when the charges span a wide range of
+// magnitudes: the 32-bit unit follows the largest |q|, so when that exceeds
+// WIDE_RANGE times the RMS |q| of all charges the typical contribution
+// would be resolved coarsely (molecular charges stay near 1, Gaussian ones
+// below 6 up to millions of charges).
+constexpr double WIDE_RANGE = 8.0;
+// ... and so does a tile whose reach bound (the most charges that can reach
+// one of its points) exceeds WIDE_REACH: the 32-bit unit grows with the
+// bound while the resolution a point needs does not (at 26 charges per mesh
+// point the 32-bit sums held the mesh charge only to 1.3e-4).  The
+// benchmark systems reach about 130.
+constexpr int WIDE_REACH = 2048;
+__device__ __forceinline__ bool wide_charge_range(const SpreadArgs& a)
+{
+    const MapGeo& g = a.g;
+    const int n = a.offsets[g.ntiles * NCLASS * g.bin_stride];
+    return n > 0 && a.stats[1] * a.stats[1] * n > WIDE_RANGE * WIDE_RANGE * a.stats[2];
+}
 template <int P>
 __device__ __forceinline__ int contribution_exponent(double qmax)
 {
@@ -438,12 +458,15 @@ __device__ __forceinline__ void spread_kernel(const SpreadArgs& a)
     const int nown = own1 - own0;
     if (sizeof(A) == 8) {
         spread_tile<P, R, long long, TAB>(a, rt, acc8, fixed_point_exponent<P, 64>(total, qmax), cur, nown, T0, ext);
-    } else if (total > WIDE_VISITS) {
+    } else if (total > WIDE_VISITS || wide_charge_range(a)) {
         spread_tile<P, R, long long, TAB>(a, rt, acc8, contribution_exponent<P>(qmax), cur, nown, T0, ext);
     } else {
         const int reach = count_pass(a, rt, occ, wmax, cur, nown, ext);
-        spread_tile<P, R, int, TAB>(a, rt, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, nown, T0,
-                                    ext);
+        if (reach > WIDE_REACH)
+            spread_tile<P, R, long long, TAB>(a, rt, acc8, contribution_exponent<P>(qmax), cur, nown, T0, ext);
+        else
+            spread_tile<P, R, int, TAB>(a, rt, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, nown,
+                                        T0, ext);
     }
 }
 
@@ -568,18 +591,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     int* occ = (int*)(smem_raw + a.occ_off);
     const int nocc = a.occ_n[0] * a.occ_n[1] * a.occ_n[2];
     // a 32-bit tile clears the first half only
-    const int nclear = nown > WIDE_VISITS ? a.box_stride : (a.box_stride + 1) / 2;
+    const bool wide = nown > WIDE_VISITS || wide_charge_range(a);
+    const int nclear = wide ? a.box_stride : (a.box_stride + 1) / 2;
     for (int i = threadIdx.x; i < nclear; i += blockDim.x) acc8[i] = 0;
     for (int i = threadIdx.x; i < nocc; i += blockDim.x) occ[i] = 0;
     __syncthreads();
     float* out = a.box + (size_t)tile * a.box_stride;
     const double qmax = a.stats[1];
-    if (nown > WIDE_VISITS) {
+    if (wide) {
         push_tile<P, long long, TAB>(a, acc8, contribution_exponent<P>(qmax), cur, own0, nown, ext, out);
     } else {
         const int reach = count_pass_own(a, rec, own0, nown, occ, wmax, cur, ext);
-        push_tile<P, int, TAB>(a, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, own0, nown, ext,
-                               out);
+        if (reach > WIDE_REACH) {
+            // 64-bit sums after all: clear the second half of the box too
+            for (int i = (a.box_stride + 1) / 2 + (int)threadIdx.x; i < a.box_stride; i += blockDim.x) acc8[i] = 0;
+            __syncthreads();
+            push_tile<P, long long, TAB>(a, acc8, contribution_exponent<P>(qmax), cur, own0, nown, ext, out);
+        } else {
+            push_tile<P, int, TAB>(a, (int*)smem_raw, fixed_point_exponent<P, 32>(reach, qmax), cur, own0, nown,
+                                   ext, out);
+        }
     }
 }
 
