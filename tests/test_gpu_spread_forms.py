@@ -7,7 +7,10 @@ when there are fewer mesh tiles than CUs; PPPM_SPREAD forces either form at
 plan creation.  Cases: the benchmark system at P = 5, 6 and 7,
 ragged meshes with axes of one tile (the boxes wrap onto the start of the
 axis), a dense cluster at P = 7 (64-bit box sums), and the mesh charge of
-the FP64 output (the fold also writes the caller's FP64 mesh)."""
+the FP64 output (the fold also writes the caller's FP64 mesh), and two
+inputs that need the 64-bit sums although their tiles stay under the
+visit count that selects them: 26 charges per mesh point, and charges
+whose magnitudes span e^+-6."""
 import os
 
 import numpy as np
@@ -135,3 +138,37 @@ def test_default_form_of_make_rho(idx, P):
         # differ, so the bits tell them apart (on 1,000 charges they can
         # coincide)
         assert not same
+
+
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_dense_mesh_in_both_forms(diff):
+    # 20,000 Gaussian charges on 8 x 8 x 12 points (26 per point): the push
+    # form's second tile holds fewer than 8,192 charges, and its reach bound
+    # sends it to the 64-bit sums (with 32-bit sums its mesh charge was off
+    # by 1.3e-4 of the maximum)
+    rng = np.random.default_rng(97)
+    lo, length = (-2.3, 8.2, 5.9), (5.78, 14.79, 11.6)
+    pos = np.asarray(lo) + rng.uniform(-0.5, 1.5, size=(20000, 3)) * np.asarray(length)
+    q = rng.normal(0, 1, size=20000)
+    out, ref = both_forms(pos, q, lo, length, (8, 8, 12), 5, 0.487, diff, f"dense 8x8x12 {diff}")
+    for form, gpu in out.items():
+        err = np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max()
+        print(f"  {form}: mesh charge {err:.2e}", flush=True)
+        assert err <= 1e-5
+
+
+def test_wide_charge_range_in_both_forms():
+    # |q| spread over e^+-6 (max |q| about 14 times the RMS), 60,000 charges
+    # mostly in one cluster on 16 x 12 x 16 points: the 32-bit unit follows
+    # max |q|, so these take the 64-bit sums in every tile
+    rng = np.random.default_rng(31)
+    lo, length = (1.0, -3.0, 2.0), (12.0, 9.0, 12.0)
+    pos = np.asarray(lo) + rng.uniform(0.0, 1.0, size=(60000, 3)) * np.asarray(length)
+    pos[:48000] = np.asarray(lo) + 0.5 * np.asarray(length) + rng.normal(0, 1, size=(48000, 3)) * 0.05 * np.asarray(length)
+    q = rng.normal(0, 1, size=60000) * np.exp(rng.uniform(-6, 6, size=60000))
+    assert np.abs(q).max() > 8 * np.sqrt((q ** 2).mean())
+    out, ref = both_forms(pos, q, lo, length, (16, 12, 16), 3, 0.28, "ad", "wide |q| 16x12x16", launch=((4, 4, 4), 1024))
+    for form, gpu in out.items():
+        err = np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max()
+        print(f"  {form}: mesh charge {err:.2e}", flush=True)
+        assert err <= 1e-5
