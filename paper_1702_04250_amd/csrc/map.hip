@@ -360,6 +360,22 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int nbins_, int nbl
     if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) offsets[nbins_] = sbase + total;
 }
 
+// A record coordinate t = s + f stored in R: when f is within half an R step
+// of 1, t rounds up to s + 1, and the kernels would decode the next point as
+// the stencil start.  The order-2 ad derivative weights jump there, so the
+// value is kept one step below s + 1 instead (f changes by at most one step
+// of t), and every kernel decodes the start the map chose.
+__device__ __forceinline__ float below_next(float t, int s)
+{
+    const float lim = (float)(s + 1);
+    return t < lim ? t : __int_as_float(__float_as_int(lim) - 1);
+}
+__device__ __forceinline__ double below_next(double t, int s)
+{
+    const double lim = (double)(s + 1);
+    return t < lim ? t : __longlong_as_double(__double_as_longlong(lim) - 1);
+}
+
 // Scatter into binned order.  Histogram form (hist != nullptr): destination
 // = bin offset + the block's offset within the bin + rank; atomic form:
 // sub-bin offset + rank.
@@ -386,9 +402,9 @@ __device__ __forceinline__ void scatter_charge(int i, const TI* __restrict__ pos
         for (int d = 0; d < 3; ++d) f[d] = floor(f[d] * (double)g.wtab_n + 0.5) / (double)g.wtab_n;
     }
     typename Rec<R>::T r;
-    r.x = (R)((double)sl[0] + f[0]);
-    r.y = (R)((double)sl[1] + f[1]);
-    r.z = (R)((double)sl[2] + f[2]);
+    r.x = below_next((R)((double)sl[0] + f[0]), sl[0]);
+    r.y = below_next((R)((double)sl[1] + f[1]), sl[1]);
+    r.z = below_next((R)((double)sl[2] + f[2]), sl[2]);
     r.w = (R)q[i];
     rec[dest] = r;
     perm[dest] = i;

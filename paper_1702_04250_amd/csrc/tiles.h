@@ -98,9 +98,8 @@ __device__ __forceinline__ int find_run(const RunTable& rt, int v)
 }
 
 // Decode one axis of a record: t = stencil start within its tile + fraction.
-// FP32 rounding may push t up to the tile edge; clamping keeps the start in
-// the tile the charge was binned in and gives f = 1, which yields the same
-// weights as f = 0 one point further.
+// The particle map stores t below s + 1, so the integer part is the start it
+// chose; the clamp to the tile is a guard.
 template <typename R>
 __device__ __forceinline__ void decode_local(R t, int ext, int& s, R& f)
 {

@@ -537,3 +537,30 @@ def test_ad_self_force_of_a_lone_charge(P):
         assert err < 1e-8
         assert before > 0 and after < {4: 0.08, 5: 0.01, 7: 0.01}[P] * before
         assert err32 < 2e-5
+
+
+@pytest.mark.parametrize("diff", ["ad", "ik"])
+def test_order_2_charges_just_below_grid_points(diff):
+    # P = 2: the ad derivative weights jump at grid points.  Charges one
+    # FP32 step below a grid point have a fraction within half a step of 1,
+    # where the stored coordinate s + f would round up to s + 1; the map keeps
+    # it below, so the gathers use the cell the map (and the oracle) chose
+    # (rounded up, single forces were off by 7 % of the RMS force)
+    rng = np.random.default_rng(12)
+    lo, length, K = (0.25, -1.5, 2.0), (16.0, 16.0, 16.0), (16, 16, 16)
+    h = np.asarray(length) / np.asarray(K)
+    pos = np.asarray(lo) + rng.uniform(0, 1, size=(3000, 3)) * np.asarray(length)
+    grid = np.asarray(lo) + rng.integers(1, 16, size=(600, 3)) * h
+    below = np.nextafter(grid.astype(np.float32), np.float32(-np.inf)).astype(np.float64)
+    pos = np.concatenate([pos, below])
+    q = rng.choice([-1.0, 1.0], size=len(pos))
+    print(f"case order 2 below grid points {diff}", flush=True)
+    pos_r, q_r = io_round(pos, q, torch.float32)
+    plan = make_plan(pkg, lo, length, K, 2, 0.6, 1.0, diff, "mixed", torch.float32, len(q))
+    gpu = gpu_run(plan, pos_r, q_r, torch.float32)
+    plan.close()
+    ref = oracle.pppm(pos_r, q_r, lo, length, K, 2, 0.6, 1.0, diff)
+    errs, bad = compare(gpu, ref, "mixed")
+    print(f"  errors {errs}", flush=True)
+    assert not bad, bad
+    assert errs["forces_max"] < 1e-4
