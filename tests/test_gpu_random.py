@@ -11,7 +11,10 @@ no relative error.  A second set draws dense systems (20,000 to 60,000
 charges on meshes of 8 to 32 points per axis, most of them clustered
 within a few cells), which exercise the 64-bit sums of crowded tiles; their
 charges are unit or Gaussian (a range of |q| over several orders of
-magnitude at that density is outside the mixed form's bound)."""
+magnitude at that density is outside the mixed form's bound).  A third set
+draws large systems (20,000 to 200,000 charges on meshes of 32 to 128 points
+per axis, up to two charges per mesh point, many tiles per axis) with the
+Ewald split drawn over a decade."""
 import os
 
 import numpy as np
@@ -83,6 +86,26 @@ def draw_dense(case):
     return P, mesh, n, diff, length, lo, pos, q, g, prec, form, launch, False
 
 
+def draw_large(case):
+    rng = np.random.default_rng(60520 + case)
+    P = int(rng.integers(2, 8))
+    mesh = tuple(int(rng.choice([32, 40, 48, 64, 72, 80, 96, 100, 128])) for _ in range(3))
+    n = int(rng.choice([20000, 100000, 200000]))
+    diff = str(rng.choice(["ad", "ik"]))
+    length = tuple(float(x) for x in rng.uniform(5.0, 30.0, size=3))
+    lo = tuple(float(x) for x in rng.uniform(-10, 10, size=3))
+    pos = np.asarray(lo) + rng.uniform(-0.5, 1.5, size=(n, 3)) * np.asarray(length)
+    q = rng.choice([-1.0, 1.0], size=n) if rng.random() < 0.5 else rng.normal(0, 1, size=n)
+    if rng.random() < 0.5:
+        q = q - q.mean()
+    h = min(length[d] / mesh[d] for d in range(3))
+    g = float(np.exp(rng.uniform(np.log(0.3), np.log(3.0))) / (h * 4))
+    prec = str(rng.choice(["mixed", "fp64"]))
+    form = str(rng.choice(["default", "visit", "push"]))
+    backward = rng.random() < 0.5
+    return P, mesh, n, diff, length, lo, pos, q, g, prec, form, None, backward
+
+
 @pytest.mark.parametrize("case", range(48))
 def test_random_case_against_the_oracle(case):
     run_case(f"random {case}", draw(case))
@@ -91,6 +114,11 @@ def test_random_case_against_the_oracle(case):
 @pytest.mark.parametrize("case", range(12))
 def test_random_dense_case_against_the_oracle(case):
     run_case(f"dense random {case}", draw_dense(case))
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_large_case_against_the_oracle(case):
+    run_case(f"large random {case}", draw_large(case))
 
 
 def run_case(label, drawn):
