@@ -120,9 +120,10 @@ constexpr double WIDE_RANGE = 8.0;
 // ... and so does a tile whose reach bound (the most charges that can reach
 // one of its points) exceeds WIDE_REACH: the 32-bit unit grows with the
 // bound while the resolution a point needs does not (at 26 charges per mesh
-// point the 32-bit sums held the mesh charge only to 1.3e-4).  The
-// benchmark systems reach about 130.
-constexpr int WIDE_REACH = 2048;
+// point the 32-bit sums held the mesh charge only to 1.3e-4; at two
+// charges per point, P = 5, to 2.0e-5, where the 64-bit sums reach 5.3e-7
+// for 2.5 % more time).  The benchmark systems reach about 130.
+constexpr int WIDE_REACH = 512;
 __device__ __forceinline__ bool wide_charge_range(const SpreadArgs& a)
 {
     const MapGeo& g = a.g;

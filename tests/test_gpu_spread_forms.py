@@ -9,8 +9,8 @@ ragged meshes with axes of one tile (the boxes wrap onto the start of the
 axis), a dense cluster at P = 7 (64-bit box sums), and the mesh charge of
 the FP64 output (the fold also writes the caller's FP64 mesh), and two
 inputs that need the 64-bit sums although their tiles stay under the
-visit count that selects them: 26 charges per mesh point, and charges
-whose magnitudes span e^+-6."""
+visit count that selects them: 26 charges per mesh point, two charges per
+mesh point on 64^3, and charges whose magnitudes span e^+-6."""
 import os
 
 import numpy as np
@@ -172,3 +172,19 @@ def test_wide_charge_range_in_both_forms():
         err = np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max()
         print(f"  {form}: mesh charge {err:.2e}", flush=True)
         assert err <= 1e-5
+
+
+def test_two_charges_per_point_in_both_forms():
+    # 524,288 Gaussian charges on 64^3 points (two per point, eight times the
+    # benchmark system's density): the reach bound exceeds the 32-bit switch,
+    # so both forms sum in 64 bits (with 32-bit sums the visit form's mesh
+    # charge was off by 2.0e-5 of the maximum)
+    rng = np.random.default_rng(5)
+    lo, length = (0.0, 0.0, 0.0), (40.0, 40.0, 40.0)
+    pos = rng.uniform(0, 40, size=(524288, 3))
+    q = rng.normal(0, 1, size=524288)
+    out, ref = both_forms(pos, q, lo, length, (64, 64, 64), 5, 0.5, "ad", "two per point 64^3")
+    for form, gpu in out.items():
+        err = np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max()
+        print(f"  {form}: mesh charge {err:.2e}", flush=True)
+        assert err <= 2e-6
