@@ -88,8 +88,10 @@ typedef enum { PPPM_DIFF_IK = 0, PPPM_DIFF_AD = 1 } pppm_diff;
 /* Arithmetic of the particle-mesh steps.
  *   FP64:  every step in double precision.
  *   MIXED: stencil weights and their products in FP32, rounded without
- *          bias to a fixed-point unit and summed exactly in LDS (32-bit sums,
- *          64-bit in tiles that read more than 8,192 charges); each mesh point
+ *          bias to a fixed-point unit and summed exactly in LDS (32-bit sums;
+ *          64-bit in tiles that read more than 8,192 charges or where more
+ *          than 512 charges can reach one point, and in every tile when the
+ *          largest |q| exceeds 8 times the RMS |q|); each mesh point
  *          is flushed as FP64 (the caller's rho) and as FP32 (the plan's FFT
  *          input); FFTs, field meshes and gathers in FP32; the energy
  *          reduction in FP64. */
