@@ -35,6 +35,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PROFILE = os.path.join(ROOT, "profiles", "step_kernels_uniform524k_K128_P5_ad_mixed.md")
 # kernel symbol of each timed step (one launch per call)
 STEP_KERNEL = {"make_rho": "k_spread", "fieldforce_ad": "k_gather"}
+# the committed profile summaries that the roofline entry reads cover the
+# default order; at P >= 6 the plan spreads with k_spread_push + k_fold
+PROFILE_ORDER = 5
 METRIC = "particles/s for make_rho+fieldforce (ik & ad) at P=5; % HBM peak; FP32 vs FP64 error"
 
 
@@ -138,8 +141,8 @@ def summarize(folder):
     out.append("")
     out.append("| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/launch (calibrated) |")
     out.append("|---|---|---|---|")
-    for k in ("k_spread", "k_gather", "k_hist_count", "k_scatter_scan", "k_scatter", "k_map_count",
-              "k_fft_xy_fwd", "k_fft_z_solve", "k_fft_yx_inv"):
+    for k in ("k_spread", "k_spread_push", "k_fold", "k_gather", "k_hist_count", "k_scatter_scan", "k_scatter",
+              "k_map_count", "k_fft_xy_fwd", "k_fft_z_solve", "k_fft_yx_inv"):
         f, _ = _counter_per_dispatch(os.path.join(folder, "fetch"), "FETCH_SIZE", k)
         w, _ = _counter_per_dispatch(os.path.join(folder, "write"), "WRITE_SIZE", k)
         if f is None or w is None or not cal["FETCH_SIZE"] or not cal["WRITE_SIZE"]:
@@ -598,6 +601,8 @@ def main():
     b_ff = algorithmic_bytes("fieldforce_ad", n, cells, "mixed")
     dom, t_dom, b_dom = ("make_rho", t_rho, b_rho) if t_rho >= t_ff else ("fieldforce_ad", t_ff, b_ff)
     achieved = b_dom / (t_dom * 1e-6) / 1e9
+    dom_kernel = STEP_KERNEL[dom] if (dom != "make_rho" or order <= 5) else "k_spread_push + k_fold"
+    profiled = order == PROFILE_ORDER
     out = {
         "metric": METRIC,
         "value": n / (head["ms_per_step"] * 1e-3),
@@ -615,11 +620,12 @@ def main():
                    "diff": "ad", "prec": "mixed (f32 stencils with unbiased fixed-point LDS sums, f32 gathers "
                                          "and FFTs; f64 energy)",
                    "io_dtype": "f32", "step": "particle_map + make_rho + poisson + fieldforce"},
-        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(STEP_KERNEL[dom]),
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(dom_kernel) if profiled else None,
                      "algorithmic_bytes_per_launch": b_dom, "avg_launch_us": t_dom,
                      "timing": "HIP events around back-to-back launches of the step on the plan's stream",
-                     "profile_avg_launch_us": recorded_avg_us(STEP_KERNEL[dom])},
+                     "profile_avg_launch_us": recorded_avg_us(dom_kernel) if profiled else None},
         "kernels_us": {k[:-3]: v for k, v in head.items() if k.endswith("_us") and k != "wall_ms_per_step"},
         "kernel_loop_us": k_ad,
         "step_us_p10_p50_p90": head["step_us_p10_p50_p90"],
